@@ -1,0 +1,180 @@
+/*
+ * blest.h - C-ABI of libblest, a pull-based breadth-first search over Binarised
+ * Virtual Slice Sets (BVSS) for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Elbek and Kaya, "BLEST: Blazingly Efficient BFS using Tensor Cores".
+ *   - BFS as repeated Boolean-semiring products y = A (x) x with A the adjacency of
+ *     the transposed graph (Section 2).
+ *   - Slices, slice sets and virtual slice sets (Sections 2 and 2.1); column-major
+ *     placement of a VSS's row-sorted slices (Section 2.1.2).
+ *   - Compression-oriented reordering (Algorithm 1, JaccardWithWindows) for
+ *     social-like graphs and bandwidth-reducing reordering (RCM) otherwise
+ *     (Sections 2.2 and 2.2.1).
+ *   - The eager kernel (Algorithm 2) and the lazy vertex-update kernel
+ *     (Algorithm 3, Section 3.2), all levels fused into one persistent launch
+ *     (Section 3.3).
+ *   - Multi-source BFS stacks the frontiers column-wise into a frontier matrix
+ *     (Section 2); here up to 64 sources share one launch.
+ *
+ * Conventions common to every call
+ *   - Vertices are 0 .. n-1.  The input CSR lists OUT-neighbours; BFS follows
+ *     out-edges.  Self-loops and duplicate arcs are accepted and dropped.
+ *   - Levels are int32 in the caller's (original) vertex IDs; -1 = unreachable;
+ *     the source has level 0.
+ *   - Device pointers are plain HIP device addresses; `stream` is a hipStream_t
+ *     passed as void* (NULL = the null stream).  BFS calls are asynchronous on
+ *     that stream; argument errors are returned synchronously before anything is
+ *     enqueued; a launch failure returns BLEST_ERR_DEVICE.
+ *   - No C++ exception crosses this interface.  Every call is thread-safe for
+ *     distinct handles; calls on one handle from several host threads must be
+ *     serialised by the caller.
+ */
+#ifndef BLEST_H
+#define BLEST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct blest_graph* blest_handle;
+
+typedef enum {
+  BLEST_OK = 0,
+  BLEST_ERR_INVALID_ARGUMENT = 1, /* null pointer, source >= n, k out of range, ... */
+  BLEST_ERR_INVALID_GRAPH = 2,    /* row_ptr not monotone, row_ptr[n] != nnz, col >= n */
+  BLEST_ERR_TOO_LARGE = 3,        /* nnz >= 2^32 (the paper's |E| <= 2^32 - 1 limit) */
+  BLEST_ERR_OUT_OF_MEMORY = 4,    /* host or device allocation failed */
+  BLEST_ERR_BUDGET = 5,           /* a request exceeds the configured device budget */
+  BLEST_ERR_DEVICE = 6,           /* a HIP call or kernel launch failed */
+  BLEST_ERR_NO_DEVICE = 7,        /* handle built host-only (device = -1) or no GPU */
+  BLEST_ERR_INTERNAL = 8
+} blest_status;
+
+/* Orderings (Section 2.2).  AUTO applies the paper's static rule (Section 2.2.1):
+ * social-like graphs get Algorithm 1, others reverse Cuthill-McKee. */
+enum {
+  BLEST_REORDER_AUTO = 0,
+  BLEST_REORDER_NONE = 1,
+  BLEST_REORDER_COMPRESSION = 2, /* Algorithm 1, JaccardWithWindows */
+  BLEST_REORDER_BANDWIDTH = 3    /* reverse Cuthill-McKee */
+};
+
+/* Vertex-update schemes.  AUTO: lazy (Algorithm 3) iff the graph is social-like
+ * and its update divergence exceeds 25,000 (Section 4, discussion of Table 3);
+ * otherwise eager (Algorithm 2). */
+enum { BLEST_UPDATE_AUTO = 0, BLEST_UPDATE_EAGER = 1, BLEST_UPDATE_LAZY = 2 };
+
+typedef struct {
+  uint32_t sigma;      /* slice width in columns: 8 (the paper's value), 16 or 32 */
+  uint32_t slots;      /* slices per lane of a 64-lane wavefront: tau = 64 * slots (1..8) */
+  uint32_t window;     /* Algorithm 1 window w, a multiple of sigma (default 65536) */
+  int32_t reorder;     /* BLEST_REORDER_* */
+  int32_t update;      /* BLEST_UPDATE_* */
+  int32_t device;      /* HIP device ordinal; -1 builds host-only (structure and stats) */
+  uint32_t threads;    /* host threads for the build (0 = all hardware threads) */
+  uint32_t block;      /* threads per workgroup of the persistent kernels (0 = 512) */
+  uint32_t blocks_per_cu; /* persistent workgroups per compute unit (0 = 2) */
+} blest_options;
+
+typedef struct {
+  uint32_t n;
+  uint64_t m;                   /* arcs after dropping loops and duplicates */
+  uint32_t sigma, tau, lanes;
+  uint32_t num_slice_sets;      /* ceil(n / sigma) */
+  uint32_t num_vss;
+  uint64_t num_slices;          /* stored = unpadded slices (the layout pads nothing) */
+  double compression;           /* m / (num_slices * sigma)            (Section 2.2) */
+  double u_div_paper;           /* update divergence, 32 lanes x 32/sigma slots (Section 2.2.1) */
+  double u_div_native;          /* same metric on this layout (64 lanes x slots) */
+  int32_t social_like;          /* Section 2.2.1 test */
+  int32_t reorder_used;         /* BLEST_REORDER_* actually applied */
+  int32_t update_used;          /* BLEST_UPDATE_* actually used */
+  uint64_t bvss_device_bytes;   /* static arrays resident on the device */
+  uint64_t bvss_bytes_table3;   /* the paper's accounting (Table 3) for this structure */
+  double reorder_seconds;       /* host ordering time */
+  double build_seconds;         /* host BVSS construction time (after ordering) */
+} blest_stats_t;
+
+/* Fills *opt with the defaults listed above. */
+void blest_default_options(blest_options* opt);
+
+/* Builds the reordered BVSS of G = (V, E) and, unless opt->device == -1, uploads
+ * it to that device.  row_ptr (n + 1 entries) and col_idx (nnz entries) are HOST
+ * arrays holding the out-neighbour CSR; they are copied, so the caller may free
+ * them on return.  opt may be NULL (defaults).  On success *out owns all device
+ * memory of the graph; release it with blest_destroy.  Errors: INVALID_ARGUMENT
+ * (null pointers, n == 0, bad option values), INVALID_GRAPH, TOO_LARGE,
+ * OUT_OF_MEMORY, DEVICE. */
+blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, const uint32_t* col_idx,
+                         const blest_options* opt, blest_handle* out);
+
+/* Single-source BFS (Algorithm 2 or 3, per the handle's update scheme).
+ * levels_out: DEVICE int32[n], caller-owned, fully overwritten.
+ * parents_out: DEVICE int32[n] or NULL; if given, parents_out[v] is the smallest
+ * original ID among v's in-neighbours one level closer to the source, the source's
+ * parent is itself, and -1 marks unreached vertices.
+ * Errors: INVALID_ARGUMENT (source >= n, null levels_out), NO_DEVICE, DEVICE. */
+blest_status blest_bfs(blest_handle h, uint32_t source, int32_t* levels_out, int32_t* parents_out,
+                       void* stream);
+
+/* k-source BFS in one launch: sources is a HOST array of k vertex IDs
+ * (1 <= k <= 64, repeats allowed); levels_out is DEVICE int32[k * n], row j
+ * (levels_out[j*n .. j*n+n-1]) belongs to sources[j].  The frontiers form an
+ * n x k bit-matrix (Section 2); each level is one Boolean SpMM over the BVSS.
+ * Errors: INVALID_ARGUMENT, NO_DEVICE, DEVICE. */
+blest_status blest_bfs_multi(blest_handle h, const uint32_t* sources, uint32_t k, int32_t* levels_out,
+                             void* stream);
+
+/* One launch running g independent single-source BFSs, BFS i on graph hs[i] from
+ * sources[i] (a HOST array), writing DEVICE int32[n_i] at levels_out[i] (a HOST
+ * array of g device pointers).  All handles must live on the same device.  Each
+ * BFS is owned by one workgroup whose bitmaps live in LDS, so graphs must have
+ * n <= 131072; larger ones return INVALID_ARGUMENT.  The launch is an ordinary
+ * (non-cooperative) kernel, so it can be captured into a HIP graph. */
+blest_status blest_bfs_many(const blest_handle* hs, const uint32_t* sources, uint32_t g,
+                            int32_t* const* levels_out, void* stream);
+
+/* Structure statistics of a built handle (host-side, no device access). */
+blest_status blest_stats(blest_handle h, blest_stats_t* out);
+
+/* Device bytes a k-source call on this handle needs beyond the resident BVSS
+ * (frontier/visited bitmaps, queues, and k * n * 4 bytes of levels), for
+ * admission control.  k = 0 reports the resident BVSS bytes alone. */
+blest_status blest_footprint(blest_handle h, uint32_t k, uint64_t* device_bytes);
+
+/* Host copies of internal arrays, for structural tests and accounting.
+ * which: BLEST_EXPORT_*; dst may be NULL to query *size_bytes; otherwise at most
+ * capacity_bytes are copied. */
+enum {
+  BLEST_EXPORT_NEW_ID = 0,          /* uint32[n]: new label of each original vertex */
+  BLEST_EXPORT_REAL_PTRS = 1,       /* uint32[num_slice_sets + 1] */
+  BLEST_EXPORT_VIRTUAL_TO_REAL = 2, /* uint32[num_vss] */
+  BLEST_EXPORT_VSS_BEGIN = 3,       /* uint32[num_vss + 1]: first slice of each VSS */
+  BLEST_EXPORT_ROW_IDS = 4,         /* uint32[num_slices], new labels */
+  BLEST_EXPORT_MASKS = 5            /* sigma/8 bytes per slice, little-endian, bit j = column j */
+};
+blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t capacity_bytes,
+                          uint64_t* size_bytes);
+
+/* Algorithmic device bytes of one BFS whose result is `levels` (HOST int32[n],
+ * original IDs): for every level l and every slice set holding a vertex of level
+ * l - 1, its unpadded slices (4-byte row ID + sigma/8-byte mask), its frontier
+ * chunk and 8 bytes per VSS (queue entry + VSS metadata); plus the per-level
+ * bitmap sweeps of the lazy scheme (2 * n/8 bytes per level) and the 4n-byte
+ * level initialisation.  Lets a benchmark turn a measured time into GB/s. */
+blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint64_t* bytes);
+
+/* Releases the handle and its device memory.  NULL is ignored.  Must not be called
+ * while work using the handle is still pending on a stream. */
+void blest_destroy(blest_handle h);
+
+/* Static string naming a status code. */
+const char* blest_status_string(blest_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLEST_H */

@@ -16,7 +16,8 @@ Readings of points the paper leaves open
     power law = a least-squares line through (log d, log count(d)) over degrees
     d >= 1 with count > 0 (at least 3 such degrees) has slope in [-3.5, -1.5] and
     R^2 >= 0.9.  Social-like iff either holds.
-  * RCM: components in order of their smallest vertex ID; each starts at a
+  * RCM works on the undirected view (out- plus in-neighbours), which is the graph
+    itself for the symmetric inputs used here.  Components in order of their smallest vertex ID; each starts at a
     George-Liu pseudo-peripheral vertex found from the component's minimum-degree
     vertex (ties: smallest ID), moving to the minimum-degree vertex of the last BFS
     level while the eccentricity grows; Cuthill-McKee visits the unvisited
@@ -33,6 +34,15 @@ import numpy as np
 def _neighbours(g):
     rp = g.row_ptr
     return [set(int(x) for x in g.col[rp[v]:rp[v + 1]]) for v in range(g.n)]
+
+
+def _undirected_neighbours(g):
+    """N(v) = out(v) | in(v); RCM orders the undirected view of the graph."""
+    N = _neighbours(g)
+    for v in range(g.n):
+        for w in list(N[v]):
+            N[w].add(v)
+    return N
 
 
 def _jaccard(a: set, b: set) -> float:
@@ -121,8 +131,8 @@ def _eccentricity(N, root):
 
 
 def rcm(g) -> np.ndarray:
-    """Reverse Cuthill-McKee.  Returns new_id[old] (uint32[n])."""
-    N = [sorted(s) for s in _neighbours(g)]
+    """Reverse Cuthill-McKee on the undirected view.  Returns new_id[old] (uint32[n])."""
+    N = [sorted(s) for s in _undirected_neighbours(g)]
     deg = [len(x) for x in N]
     seen = [False] * g.n
     order = []

@@ -1,0 +1,248 @@
+"""Python binding of libblest: pull-based BFS over Binarised Virtual Slice Sets on
+MI355X (Elbek and Kaya, "BLEST: Blazingly Efficient BFS using Tensor Cores").
+
+Argument marshalling only: every step of the BFS runs in the HIP kernels behind the
+C-ABI declared in ``include/blest.h``.  PyTorch supplies device memory and streams.
+There is no CPU fallback: if ``libblest.so`` is missing or the device call fails,
+the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libblest.so")
+
+BLEST_OK = 0
+STATUS = {0: "ok", 1: "invalid argument", 2: "invalid graph", 3: "too large", 4: "out of memory",
+          5: "budget", 6: "device error", 7: "no device", 8: "internal error"}
+REORDER = {"auto": 0, "none": 1, "compression": 2, "bandwidth": 3}
+UPDATE = {"auto": 0, "eager": 1, "lazy": 2}
+EXPORT = {"new_id": (0, np.uint32), "real_ptrs": (1, np.uint32), "virtual_to_real": (2, np.uint32),
+          "vss_begin": (3, np.uint32), "row_ids": (4, np.uint32), "masks": (5, np.uint8)}
+EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_bfs_multi", "blest_bfs_many",
+                    "blest_stats", "blest_footprint", "blest_export", "blest_model_bytes", "blest_destroy",
+                    "blest_status_string")
+
+
+class BlestError(RuntimeError):
+    def __init__(self, call, status):
+        self.status = status
+        super().__init__(f"{call} failed: {STATUS.get(status, status)} ({status})")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("window", ctypes.c_uint32),
+                ("reorder", ctypes.c_int32), ("update", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("threads", ctypes.c_uint32), ("block", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint64), ("sigma", ctypes.c_uint32),
+                ("tau", ctypes.c_uint32), ("lanes", ctypes.c_uint32), ("num_slice_sets", ctypes.c_uint32),
+                ("num_vss", ctypes.c_uint32), ("num_slices", ctypes.c_uint64), ("compression", ctypes.c_double),
+                ("u_div_paper", ctypes.c_double), ("u_div_native", ctypes.c_double),
+                ("social_like", ctypes.c_int32), ("reorder_used", ctypes.c_int32), ("update_used", ctypes.c_int32),
+                ("bvss_device_bytes", ctypes.c_uint64), ("bvss_bytes_table3", ctypes.c_uint64),
+                ("reorder_seconds", ctypes.c_double), ("build_seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libblest.so (building it only if it has never been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _build
+        _build.build()
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+    p32 = ctypes.POINTER(ctypes.c_uint32)
+    L.blest_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.blest_default_options.restype = None
+    L.blest_build.argtypes = [u32, u64, p32, p32, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.blest_build.restype = ctypes.c_int
+    L.blest_bfs.argtypes = [vp, u32, vp, vp, vp]
+    L.blest_bfs.restype = ctypes.c_int
+    L.blest_bfs_multi.argtypes = [vp, p32, u32, vp, vp]
+    L.blest_bfs_multi.restype = ctypes.c_int
+    L.blest_bfs_many.argtypes = [ctypes.POINTER(vp), p32, u32, ctypes.POINTER(vp), vp]
+    L.blest_bfs_many.restype = ctypes.c_int
+    L.blest_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.blest_stats.restype = ctypes.c_int
+    L.blest_footprint.argtypes = [vp, u32, ctypes.POINTER(u64)]
+    L.blest_footprint.restype = ctypes.c_int
+    L.blest_export.argtypes = [vp, i32, vp, u64, ctypes.POINTER(u64)]
+    L.blest_export.restype = ctypes.c_int
+    L.blest_model_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(u64)]
+    L.blest_model_bytes.restype = ctypes.c_int
+    L.blest_destroy.argtypes = [vp]
+    L.blest_destroy.restype = None
+    L.blest_status_string.argtypes = [ctypes.c_int]
+    L.blest_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(call, rc):
+    if rc != BLEST_OK:
+        raise BlestError(call, rc)
+
+
+def _p32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_int32_cuda(t, numel, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous int32 CUDA tensor")
+    if t.numel() != numel:
+        raise ValueError(f"{what} must hold {numel} elements, got {t.numel()}")
+
+
+def default_options() -> Options:
+    o = Options()
+    lib().blest_default_options(ctypes.byref(o))
+    return o
+
+
+class Graph:
+    """A graph resident on one GPU as a reordered BVSS (the handle of blest_build).
+
+    `csr` is any object with `n`, `row_ptr` (uint32[n+1]) and `col` (uint32[nnz]),
+    listing out-neighbours.  device=-1 builds the host structure only (statistics
+    and exports work; BFS calls raise)."""
+
+    def __init__(self, csr, *, sigma=8, slots=4, window=1 << 16, reorder="auto", update="auto",
+                 device=0, threads=0, block=0, blocks_per_cu=0):
+        o = default_options()
+        o.sigma, o.slots, o.window = sigma, slots, window
+        o.reorder, o.update = REORDER[reorder], UPDATE[update]
+        o.device, o.threads, o.block, o.blocks_per_cu = device, threads, block, blocks_per_cu
+        rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint32)
+        col = np.ascontiguousarray(csr.col if len(csr.col) else np.zeros(1, np.uint32), dtype=np.uint32)
+        h = ctypes.c_void_p()
+        _check("blest_build", lib().blest_build(int(csr.n), int(rp[-1]), _p32(rp), _p32(col), ctypes.byref(o),
+                                                ctypes.byref(h)))
+        self._h = h
+        self.n = int(csr.n)
+        self.device = device
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph is closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().blest_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- BFS -----------------------------------------------------------------
+    def bfs(self, source: int, levels=None, parents=None, stream=None):
+        """Levels (int32 CUDA tensor [n], -1 = unreachable) from `source`; with
+        parents=True (or a tensor) also the parent array.  Asynchronous on `stream`."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if levels is None:
+            levels = torch.empty(self.n, dtype=torch.int32, device=dev)
+        _require_int32_cuda(levels, self.n, "levels")
+        par = None
+        if parents is True:
+            par = torch.empty(self.n, dtype=torch.int32, device=dev)
+        elif parents is not None and parents is not False:
+            par = parents
+            _require_int32_cuda(par, self.n, "parents")
+        _check("blest_bfs", lib().blest_bfs(self.handle, int(source), ctypes.c_void_p(levels.data_ptr()),
+                                            ctypes.c_void_p(par.data_ptr() if par is not None else 0),
+                                            _stream_ptr(stream)))
+        return (levels, par) if par is not None else levels
+
+    def bfs_multi(self, sources, levels=None, stream=None):
+        """Levels of k <= 64 sources in one launch: int32 CUDA tensor [k, n]."""
+        import torch
+        src = np.ascontiguousarray(sources, dtype=np.uint32)
+        k = int(src.size)
+        if levels is None:
+            levels = torch.empty((k, self.n), dtype=torch.int32, device=torch.device("cuda", self.device))
+        _require_int32_cuda(levels, k * self.n, "levels")
+        _check("blest_bfs_multi", lib().blest_bfs_multi(self.handle, _p32(src), k,
+                                                        ctypes.c_void_p(levels.data_ptr()), _stream_ptr(stream)))
+        return levels
+
+    # -- host-side information -------------------------------------------------
+    def stats(self) -> dict:
+        s = Stats()
+        _check("blest_stats", lib().blest_stats(self.handle, ctypes.byref(s)))
+        d = {name: getattr(s, name) for name, _ in Stats._fields_}
+        d["reorder_used"] = {v: k for k, v in REORDER.items()}[d["reorder_used"]]
+        d["update_used"] = {v: k for k, v in UPDATE.items()}[d["update_used"]]
+        return d
+
+    def footprint(self, k: int) -> int:
+        b = ctypes.c_uint64()
+        _check("blest_footprint", lib().blest_footprint(self.handle, int(k), ctypes.byref(b)))
+        return int(b.value)
+
+    def export(self, which: str) -> np.ndarray:
+        code, dt = EXPORT[which]
+        size = ctypes.c_uint64()
+        _check("blest_export", lib().blest_export(self.handle, code, None, 0, ctypes.byref(size)))
+        out = np.empty(max(size.value, 1) // np.dtype(dt).itemsize, dtype=dt)
+        _check("blest_export", lib().blest_export(self.handle, code, out.ctypes.data_as(ctypes.c_void_p),
+                                                  size.value, ctypes.byref(size)))
+        return out[: size.value // np.dtype(dt).itemsize]
+
+    def model_bytes(self, levels) -> int:
+        lv = np.ascontiguousarray(levels, dtype=np.int32)
+        if lv.size != self.n:
+            raise ValueError("levels must hold n entries")
+        b = ctypes.c_uint64()
+        _check("blest_model_bytes", lib().blest_model_bytes(self.handle,
+                                                            lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                                            ctypes.byref(b)))
+        return int(b.value)
+
+
+def bfs_many(graphs, sources, outs=None, stream=None):
+    """One launch running BFS i on graphs[i] from sources[i]; returns the list of
+    int32 CUDA level tensors."""
+    import torch
+    g = len(graphs)
+    src = np.ascontiguousarray(sources, dtype=np.uint32)
+    if src.size != g:
+        raise ValueError("one source per graph")
+    if outs is None:
+        outs = [torch.empty(gr.n, dtype=torch.int32, device=torch.device("cuda", gr.device)) for gr in graphs]
+    for gr, o in zip(graphs, outs):
+        _require_int32_cuda(o, gr.n, "levels")
+    hs = (ctypes.c_void_p * g)(*[gr.handle.value for gr in graphs])
+    ptrs = (ctypes.c_void_p * g)(*[o.data_ptr() for o in outs])
+    _check("blest_bfs_many", lib().blest_bfs_many(hs, _p32(src), g, ptrs, _stream_ptr(stream)))
+    return outs

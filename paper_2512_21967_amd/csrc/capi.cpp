@@ -1,0 +1,465 @@
+// The C-ABI of libblest (include/blest.h): argument checking, host-side build,
+// device residency, per-stream workspaces and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/blest.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+using namespace blest;
+
+namespace {
+
+// Device buffer that frees itself.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t b) {
+    bytes = b;
+    return hipMalloc(&p, b ? b : 4);
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Per-stream scratch of the single-source kernels.  Calls on one stream are
+// ordered, so reusing the stream's workspace is safe without host waits.
+struct SingleWorkspace {
+  DevBuf vis, front, queue, ctrl;
+};
+
+// Persistent launches are serialised device-wide: two persistent grids that each
+// wait for all of their workgroups could otherwise starve one another of compute
+// units.  Every persistent launch waits on the previous one's completion event.
+struct DeviceSerial {
+  std::mutex mu;
+  hipEvent_t last = nullptr;
+};
+DeviceSerial g_serial[64];
+
+}  // namespace
+
+struct blest_graph {
+  blest_options opt{};
+  uint32_t n = 0;
+  uint64_t m = 0;
+  Bvss bvss;
+  std::vector<uint32_t> new_id;   // original -> new
+  std::vector<uint32_t> orig_id;  // new -> original
+  bool identity = true;
+  bool lazy = false;
+  int social = 0;
+  int reorder_used = BLEST_REORDER_NONE;
+  double u_div_paper = 0, u_div_native = 0, compression = 0;
+  double reorder_seconds = 0, build_seconds = 0;
+  // device state
+  bool on_device = false;
+  int device = -1;
+  DevBuf d_row_ids, d_masks, d_vss_beg, d_v2r, d_real_ptrs, d_orig_id;
+  uint32_t grid = 0, block = 0;
+  std::mutex ws_mu;
+  std::map<void*, std::unique_ptr<SingleWorkspace>> single_ws;
+  uint32_t n_words() const { return (n + 31) / 32; }
+};
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+blest_status map_rc(int rc) {
+  switch (rc) {
+    case kOk: return BLEST_OK;
+    case kInvalidGraph: return BLEST_ERR_INVALID_GRAPH;
+    case kTooLarge: return BLEST_ERR_TOO_LARGE;
+    case kNoMemory: return BLEST_ERR_OUT_OF_MEMORY;
+    default: return BLEST_ERR_INTERNAL;
+  }
+}
+
+bool valid_options(const blest_options& o) {
+  if (o.sigma != 8 && o.sigma != 16 && o.sigma != 32) return false;
+  if (o.slots != 1 && o.slots != 2 && o.slots != 4 && o.slots != 8) return false;
+  if (o.window == 0 || o.window % o.sigma != 0) return false;
+  if (o.reorder < BLEST_REORDER_AUTO || o.reorder > BLEST_REORDER_BANDWIDTH) return false;
+  if (o.update < BLEST_UPDATE_AUTO || o.update > BLEST_UPDATE_LAZY) return false;
+  if (o.block % 64 != 0 || o.block > 1024) return false;
+  if (o.blocks_per_cu > 16) return false;
+  return true;
+}
+
+template <class T>
+hipError_t upload(DevBuf& d, const std::vector<T>& h) {
+  hipError_t e = d.alloc(sizeof(T) * std::max<size_t>(h.size(), 1));
+  if (e != hipSuccess) return e;
+  if (h.empty()) return hipSuccess;
+  return hipMemcpy(d.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
+}
+
+blest_status to_device(blest_graph* g) {
+  if (hipSetDevice(g->device) != hipSuccess) return BLEST_ERR_NO_DEVICE;
+  const Bvss& b = g->bvss;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(g->d_row_ids, b.row_ids);
+  if (e == hipSuccess) e = upload(g->d_masks, b.masks);
+  if (e == hipSuccess) e = upload(g->d_vss_beg, b.vss_beg);
+  if (e == hipSuccess) e = upload(g->d_v2r, b.v2r);
+  if (e == hipSuccess) e = upload(g->d_real_ptrs, b.real_ptrs);
+  if (e == hipSuccess && !g->identity) e = upload(g->d_orig_id, g->orig_id);
+  if (e == hipErrorOutOfMemory) return BLEST_ERR_OUT_OF_MEMORY;
+  if (e != hipSuccess) return BLEST_ERR_DEVICE;
+  // Persistent grid: co-resident workgroups, capped at blocks_per_cu per CU.
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess || cus <= 0)
+    return BLEST_ERR_DEVICE;
+  g->block = g->opt.block;
+  uint32_t per_cu = UINT32_MAX;
+  for (int lazy = 0; lazy < 2; ++lazy) {
+    int nb = 0;
+    const void* k = bfs_kernel_symbol(b.sigma, b.slots, lazy != 0);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)g->block, 0) != hipSuccess || nb <= 0)
+      return BLEST_ERR_DEVICE;
+    per_cu = std::min<uint32_t>(per_cu, (uint32_t)nb);
+  }
+  per_cu = std::min<uint32_t>(per_cu, g->opt.blocks_per_cu);
+  g->grid = per_cu * (uint32_t)cus;
+  g->on_device = true;
+  return BLEST_OK;
+}
+
+SingleWorkspace* single_workspace(blest_graph* g, void* stream, blest_status* st) {
+  std::lock_guard<std::mutex> lk(g->ws_mu);
+  auto it = g->single_ws.find(stream);
+  if (it != g->single_ws.end()) return it->second.get();
+  auto ws = std::make_unique<SingleWorkspace>();
+  const size_t nw = g->n_words();
+  hipError_t e = ws->vis.alloc(sizeof(uint32_t) * 2 * nw);
+  if (e == hipSuccess) e = ws->front.alloc(sizeof(uint32_t) * 3 * nw);
+  if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 3 * std::max<size_t>(g->bvss.num_vss, 1));
+  if (e == hipSuccess) e = ws->ctrl.alloc(sizeof(uint32_t) * kCtrlWords);
+  if (e == hipSuccess) e = hipMemset(ws->ctrl.p, 0, sizeof(uint32_t) * kCtrlWords);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    *st = e == hipErrorOutOfMemory ? BLEST_ERR_OUT_OF_MEMORY : BLEST_ERR_DEVICE;
+    return nullptr;
+  }
+  SingleWorkspace* raw = ws.get();
+  g->single_ws.emplace(stream, std::move(ws));
+  return raw;
+}
+
+// Makes `stream` wait for the previous persistent launch on this device, runs
+// `launch`, and records the new tail event.
+template <class F>
+hipError_t serial_launch(int device, hipStream_t stream, F&& launch) {
+  DeviceSerial& ds = g_serial[device & 63];
+  std::lock_guard<std::mutex> lk(ds.mu);
+  hipError_t e = hipSuccess;
+  if (!ds.last) {
+    e = hipEventCreateWithFlags(&ds.last, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  } else {
+    e = hipStreamWaitEvent(stream, ds.last, 0);
+    if (e != hipSuccess) return e;
+  }
+  e = launch();
+  if (e != hipSuccess) return e;
+  return hipEventRecord(ds.last, stream);
+}
+
+BfsParams base_params(const blest_graph* g) {
+  BfsParams p{};
+  p.row_ids = g->d_row_ids.as<uint32_t>();
+  p.masks = g->d_masks.p;
+  p.vss_beg = g->d_vss_beg.as<uint32_t>();
+  p.v2r = g->d_v2r.as<uint32_t>();
+  p.real_ptrs = g->d_real_ptrs.as<uint32_t>();
+  p.orig_id = g->identity ? nullptr : g->d_orig_id.as<uint32_t>();
+  p.n = g->n;
+  p.n_words = g->n_words();
+  p.num_sets = g->bvss.num_sets;
+  p.num_vss = g->bvss.num_vss;
+  p.qcap = std::max<uint32_t>(g->bvss.num_vss, 1);
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+void blest_default_options(blest_options* o) {
+  if (!o) return;
+  o->sigma = 8;
+  o->slots = 4;
+  o->window = 1u << 16;
+  o->reorder = BLEST_REORDER_AUTO;
+  o->update = BLEST_UPDATE_AUTO;
+  o->device = 0;
+  o->threads = 0;
+  o->block = 512;
+  o->blocks_per_cu = 2;
+}
+
+blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, const uint32_t* col_idx,
+                         const blest_options* opt, blest_handle* out) {
+  if (!out) return BLEST_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (n == 0 || !row_ptr || (nnz > 0 && !col_idx)) return BLEST_ERR_INVALID_ARGUMENT;
+  if (nnz > 0xFFFFFFFFull) return BLEST_ERR_TOO_LARGE;
+  blest_options o;
+  blest_default_options(&o);
+  if (opt) o = *opt;
+  if (o.block == 0) o.block = 512;
+  if (o.blocks_per_cu == 0) o.blocks_per_cu = 2;
+  if (!valid_options(o)) return BLEST_ERR_INVALID_ARGUMENT;
+  std::unique_ptr<blest_graph> g;
+  try {
+    g = std::make_unique<blest_graph>();
+    g->opt = o;
+    g->n = n;
+    const int T = (int)o.threads;
+    Csr csr;
+    int rc = normalise(n, nnz, row_ptr, col_idx, T, csr);
+    if (rc != kOk) return map_rc(rc);
+    g->m = csr.nnz();
+    double t0 = now_s();
+    g->social = social_like(csr) ? 1 : 0;
+    int reorder = o.reorder;
+    if (reorder == BLEST_REORDER_AUTO) reorder = g->social ? BLEST_REORDER_COMPRESSION : BLEST_REORDER_BANDWIDTH;
+    g->reorder_used = reorder;
+    Csr work;
+    if (reorder == BLEST_REORDER_NONE) {
+      work = std::move(csr);
+    } else {
+      Csr gt;
+      transpose(csr, gt);
+      if (reorder == BLEST_REORDER_COMPRESSION) {
+        jaccard_windows(csr, gt, o.sigma, o.window, T, g->new_id);
+      } else {
+        Csr und;
+        undirected(csr, gt, und);
+        rcm(und, g->new_id);
+      }
+      relabel(csr, g->new_id, T, work);
+      g->identity = false;
+      g->orig_id.assign(n, 0);
+      for (uint32_t v = 0; v < n; ++v) g->orig_id[g->new_id[v]] = v;
+    }
+    if (g->identity) {
+      g->new_id.resize(n);
+      for (uint32_t v = 0; v < n; ++v) g->new_id[v] = v;
+    }
+    double t1 = now_s();
+    g->reorder_seconds = t1 - t0;
+    rc = build_bvss(work, o.sigma, o.slots, T, g->bvss);
+    if (rc != kOk) return map_rc(rc);
+    g->build_seconds = now_s() - t1;
+    g->compression = g->bvss.num_slices ? (double)g->m / ((double)g->bvss.num_slices * o.sigma) : 0.0;
+    g->u_div_paper = update_divergence(g->bvss, 32, 32 / o.sigma);
+    g->u_div_native = update_divergence(g->bvss, 64, o.slots);
+    if (o.update == BLEST_UPDATE_AUTO)
+      g->lazy = g->social && g->u_div_paper > 25000.0;
+    else
+      g->lazy = o.update == BLEST_UPDATE_LAZY;
+    if (o.device >= 0) {
+      g->device = o.device;
+      blest_status st = to_device(g.get());
+      if (st != BLEST_OK) return st;
+    }
+  } catch (const std::bad_alloc&) {
+    return BLEST_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    return BLEST_ERR_INTERNAL;
+  }
+  *out = g.release();
+  return BLEST_OK;
+}
+
+blest_status blest_bfs(blest_handle h, uint32_t source, int32_t* levels_out, int32_t* parents_out,
+                       void* stream) {
+  if (!h || !levels_out) return BLEST_ERR_INVALID_ARGUMENT;
+  if (source >= h->n) return BLEST_ERR_INVALID_ARGUMENT;
+  if (!h->on_device) return BLEST_ERR_NO_DEVICE;
+  try {
+    if (hipSetDevice(h->device) != hipSuccess) return BLEST_ERR_DEVICE;
+    blest_status st = BLEST_OK;
+    SingleWorkspace* ws = single_workspace(h, stream, &st);
+    if (!ws) return st;
+    BfsParams p = base_params(h);
+    p.vis = ws->vis.as<uint32_t>();
+    p.front = ws->front.as<uint32_t>();
+    p.queue = ws->queue.as<uint32_t>();
+    p.ctrl = ws->ctrl.as<uint32_t>();
+    p.levels = levels_out;
+    p.src = h->new_id[source];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = serial_launch(h->device, s, [&] {
+      return launch_bfs(p, h->bvss.sigma, h->bvss.slots, h->lazy, h->grid, h->block, s);
+    });
+    if (e == hipSuccess && parents_out) e = launch_parents(p, h->bvss.sigma, levels_out, parents_out, s);
+    return e == hipSuccess ? BLEST_OK : BLEST_ERR_DEVICE;
+  } catch (...) {
+    return BLEST_ERR_INTERNAL;
+  }
+}
+
+blest_status blest_bfs_multi(blest_handle h, const uint32_t* sources, uint32_t k, int32_t* levels_out,
+                             void* stream) {
+  if (!h || !sources || !levels_out || k == 0 || k > 64) return BLEST_ERR_INVALID_ARGUMENT;
+  for (uint32_t j = 0; j < k; ++j)
+    if (sources[j] >= h->n) return BLEST_ERR_INVALID_ARGUMENT;
+  if (!h->on_device) return BLEST_ERR_NO_DEVICE;
+  (void)stream;
+  return BLEST_ERR_INTERNAL;
+}
+
+blest_status blest_bfs_many(const blest_handle* hs, const uint32_t* sources, uint32_t g,
+                            int32_t* const* levels_out, void* stream) {
+  if (!hs || !sources || !levels_out || g == 0) return BLEST_ERR_INVALID_ARGUMENT;
+  for (uint32_t i = 0; i < g; ++i) {
+    if (!hs[i] || !levels_out[i] || sources[i] >= hs[i]->n) return BLEST_ERR_INVALID_ARGUMENT;
+    if (!hs[i]->on_device) return BLEST_ERR_NO_DEVICE;
+  }
+  (void)stream;
+  return BLEST_ERR_INTERNAL;
+}
+
+blest_status blest_stats(blest_handle h, blest_stats_t* o) {
+  if (!h || !o) return BLEST_ERR_INVALID_ARGUMENT;
+  std::memset(o, 0, sizeof(*o));
+  const Bvss& b = h->bvss;
+  o->n = h->n;
+  o->m = h->m;
+  o->sigma = b.sigma;
+  o->tau = b.tau;
+  o->lanes = 64;
+  o->num_slice_sets = b.num_sets;
+  o->num_vss = b.num_vss;
+  o->num_slices = b.num_slices;
+  o->compression = h->compression;
+  o->u_div_paper = h->u_div_paper;
+  o->u_div_native = h->u_div_native;
+  o->social_like = h->social;
+  o->reorder_used = h->reorder_used;
+  o->update_used = h->lazy ? BLEST_UPDATE_LAZY : BLEST_UPDATE_EAGER;
+  o->bvss_device_bytes = b.num_slices * (4 + b.sigma / 8) + 4ull * (2ull * b.num_vss + 1) +
+                         4ull * (b.num_sets + 1) + (h->identity ? 0 : 4ull * h->n);
+  o->bvss_bytes_table3 = b.num_slices * (4 + b.sigma / 8) + 4ull * (b.num_vss + b.num_sets);
+  o->reorder_seconds = h->reorder_seconds;
+  o->build_seconds = h->build_seconds;
+  return BLEST_OK;
+}
+
+blest_status blest_footprint(blest_handle h, uint32_t k, uint64_t* bytes) {
+  if (!h || !bytes || k > 64) return BLEST_ERR_INVALID_ARGUMENT;
+  blest_stats_t s;
+  blest_stats(h, &s);
+  if (k == 0) {
+    *bytes = s.bvss_device_bytes;
+    return BLEST_OK;
+  }
+  const uint64_t nw = h->n_words();
+  const uint64_t q = 3ull * std::max<uint32_t>(h->bvss.num_vss, 1) * 4;
+  uint64_t ws;
+  if (k == 1)
+    ws = 5 * nw * 4 + q + kCtrlWords * 4;
+  else
+    ws = 3ull * h->n * 8 + q + kCtrlWords * 4;  // 64-bit frontier/visited rows
+  *bytes = ws + (uint64_t)k * h->n * 4;
+  return BLEST_OK;
+}
+
+blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t cap, uint64_t* size) {
+  if (!h || !size) return BLEST_ERR_INVALID_ARGUMENT;
+  const void* src = nullptr;
+  uint64_t bytes = 0;
+  const Bvss& b = h->bvss;
+  switch (which) {
+    case BLEST_EXPORT_NEW_ID: src = h->new_id.data(); bytes = 4ull * h->new_id.size(); break;
+    case BLEST_EXPORT_REAL_PTRS: src = b.real_ptrs.data(); bytes = 4ull * b.real_ptrs.size(); break;
+    case BLEST_EXPORT_VIRTUAL_TO_REAL: src = b.v2r.data(); bytes = 4ull * b.v2r.size(); break;
+    case BLEST_EXPORT_VSS_BEGIN: src = b.vss_beg.data(); bytes = 4ull * b.vss_beg.size(); break;
+    case BLEST_EXPORT_ROW_IDS: src = b.row_ids.data(); bytes = 4ull * b.row_ids.size(); break;
+    case BLEST_EXPORT_MASKS: src = b.masks.data(); bytes = b.masks.size(); break;
+    default: return BLEST_ERR_INVALID_ARGUMENT;
+  }
+  *size = bytes;
+  if (dst) std::memcpy(dst, src, std::min(cap, bytes));
+  return BLEST_OK;
+}
+
+blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint64_t* bytes) {
+  if (!h || !levels || !bytes) return BLEST_ERR_INVALID_ARGUMENT;
+  const Bvss& b = h->bvss;
+  // Deepest level and, per slice set, the set of levels present among its vertices.
+  int32_t maxl = 0;
+  for (uint32_t v = 0; v < h->n; ++v) maxl = std::max(maxl, levels[v]);
+  uint64_t total = 0;
+  std::vector<int32_t> lv(h->n);
+  for (uint32_t v = 0; v < h->n; ++v) lv[h->new_id[v]] = levels[v];
+  const uint64_t per_slice = 4 + b.sigma / 8;
+  for (uint32_t s = 0; s < b.num_sets; ++s) {
+    const uint32_t nv = b.real_ptrs[s + 1] - b.real_ptrs[s];
+    if (nv == 0) continue;
+    const uint64_t slices = b.set_beg[s + 1] - b.set_beg[s];
+    // the set is active at iteration l + 1 for each distinct level l of its vertices
+    int32_t seen[64];
+    int ns = 0;
+    const uint32_t v0 = s * b.sigma, v1 = std::min<uint32_t>(h->n, v0 + b.sigma);
+    for (uint32_t v = v0; v < v1; ++v) {
+      int32_t l = lv[v];
+      if (l < 0) continue;
+      bool dup = false;
+      for (int i = 0; i < ns; ++i) dup |= seen[i] == l;
+      if (!dup) seen[ns++] = l;
+    }
+    total += (uint64_t)ns * (slices * per_slice + b.sigma / 8 + 8ull * nv);
+  }
+  const uint64_t iters = (uint64_t)maxl + 1;
+  if (h->lazy) total += iters * 2ull * ((h->n + 7) / 8);
+  total += 4ull * h->n;
+  *bytes = total;
+  return BLEST_OK;
+}
+
+void blest_destroy(blest_handle h) {
+  if (!h) return;
+  if (h->on_device) (void)hipSetDevice(h->device);
+  delete h;
+}
+
+const char* blest_status_string(blest_status s) {
+  switch (s) {
+    case BLEST_OK: return "ok";
+    case BLEST_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case BLEST_ERR_INVALID_GRAPH: return "invalid graph";
+    case BLEST_ERR_TOO_LARGE: return "graph too large (nnz >= 2^32)";
+    case BLEST_ERR_OUT_OF_MEMORY: return "out of memory";
+    case BLEST_ERR_BUDGET: return "device budget exceeded";
+    case BLEST_ERR_DEVICE: return "device error";
+    case BLEST_ERR_NO_DEVICE: return "no device (host-only handle or no GPU)";
+    case BLEST_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal declarations shared by the host-side builder (host.cpp), the HIP kernels
+// (kernels.hip) and the C-ABI (capi.cpp).  Not part of the public interface.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace blest {
+
+// Out-neighbour CSR with sorted, duplicate-free rows and no self-loops.
+struct Csr {
+  uint32_t n = 0;
+  std::vector<uint32_t> rp;   // n + 1
+  std::vector<uint32_t> col;  // rp[n]
+  uint64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+// Result codes of the host helpers (mapped onto blest_status by the C-ABI).
+enum HostRc { kOk = 0, kInvalidGraph = 2, kTooLarge = 3, kNoMemory = 4 };
+
+// Validates a caller CSR and writes its normal form (loops and duplicates dropped,
+// rows sorted).
+int normalise(uint32_t n, uint64_t nnz, const uint32_t* rp, const uint32_t* col, int threads, Csr& out);
+
+// In-neighbour CSR (the transposed graph).
+void transpose(const Csr& g, Csr& t);
+
+// Undirected view: N(v) = out(v) union in(v).
+void undirected(const Csr& g, const Csr& gt, Csr& u);
+
+// Vertex v gets label new_id[v]; rows stay sorted.
+void relabel(const Csr& g, const std::vector<uint32_t>& new_id, int threads, Csr& out);
+
+// Social-like test of Section 2.2.1 (heavy tail or power-law fit).
+bool social_like(const Csr& g);
+
+// Algorithm 1 (JaccardWithWindows).  gt is the in-neighbour CSR.  Output: new_id.
+void jaccard_windows(const Csr& g, const Csr& gt, uint32_t sigma, uint32_t w, int threads,
+                     std::vector<uint32_t>& new_id);
+
+// Reverse Cuthill-McKee on the undirected view u.  Output: new_id.
+void rcm(const Csr& u, std::vector<uint32_t>& new_id);
+
+// The static BVSS arrays (Section 2.1) in this library's layout: the slices of a
+// slice set are sorted by row and cut into VSSs of at most tau = 64 * slots; VSS v
+// owns slices [vss_beg[v], vss_beg[v+1]) stored contiguously, so lane l of a
+// wavefront handles slices l, l + 64, ... of the VSS (column-major placement,
+// Section 2.1.2) and nothing is padded.
+struct Bvss {
+  uint32_t n = 0, sigma = 8, slots = 4, tau = 256;
+  uint32_t num_sets = 0, num_vss = 0;
+  uint64_t num_slices = 0;
+  std::vector<uint32_t> real_ptrs;  // num_sets + 1
+  std::vector<uint32_t> v2r;        // num_vss
+  std::vector<uint32_t> vss_beg;    // num_vss + 1
+  std::vector<uint32_t> set_beg;    // num_sets + 1 (first slice of each set)
+  std::vector<uint32_t> row_ids;    // num_slices
+  std::vector<uint8_t> masks;       // num_slices * sigma / 8
+  uint32_t mask_bytes() const { return sigma / 8; }
+  uint64_t mask_of(uint64_t k) const {
+    uint64_t m = 0;
+    for (uint32_t b = 0; b < sigma / 8; ++b) m |= (uint64_t)masks[k * (sigma / 8) + b] << (8 * b);
+    return m;
+  }
+};
+
+int build_bvss(const Csr& g, uint32_t sigma, uint32_t slots, int threads, Bvss& out);
+
+// Update divergence (Section 2.2.1) when each set's sorted slices are cut into
+// VSSs of lanes * slots_per_lane and columns of `lanes` consecutive slices.
+double update_divergence(const Bvss& b, uint32_t lanes, uint32_t slots_per_lane);
+
+}  // namespace blest

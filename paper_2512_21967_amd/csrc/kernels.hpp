@@ -1,0 +1,50 @@
+// Device-side entry points of libblest (defined in kernels.hip), called by capi.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace blest {
+
+// Control block shared by the persistent kernels (uint32 words).  Each counter
+// sits on its own 128-byte line.
+constexpr uint32_t kLine = 32;                       // uint32 per 128-byte line
+constexpr uint32_t kBarGroups = 8;                   // one arrival counter per XCD
+constexpr uint32_t kBarRoot = kBarGroups * kLine;    // root arrival counter
+constexpr uint32_t kBarGen = kBarRoot + kLine;       // generation word
+constexpr uint32_t kQlen = kBarGen + kLine;          // 4 queue-length counters
+constexpr uint32_t kCtrlWords = kQlen + 4 * kLine;
+
+struct BfsParams {
+  // static BVSS (read-only during a launch)
+  const uint32_t* row_ids;
+  const void* masks;
+  const uint32_t* vss_beg;
+  const uint32_t* v2r;
+  const uint32_t* real_ptrs;
+  const uint32_t* orig_id;  // new label -> original ID; nullptr = identity
+  // per-call workspace
+  uint32_t* vis;            // lazy: 2 * n_words (current/next interleaved); eager: n_words
+  uint32_t* front;          // lazy: n_words; eager: 3 * n_words
+  uint32_t* queue;          // 3 * qcap
+  uint32_t* ctrl;           // kCtrlWords
+  int32_t* levels;          // n, original IDs
+  uint32_t n, n_words, num_sets, num_vss, qcap;
+  uint32_t src;             // source, new label
+};
+
+// Persistent single-source BFS; lazy selects Algorithm 3, otherwise Algorithm 2.
+// grid must be co-resident (the call uses a cooperative launch).
+hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, bool lazy, uint32_t grid,
+                      uint32_t block, hipStream_t stream);
+
+// Returns the kernel symbol used by launch_bfs (for occupancy queries).
+const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy);
+
+// Parents post-pass: parent[v] = smallest original ID among the in-neighbours of v
+// on level level[v] - 1.  Ordinary launches on `stream`.
+hipError_t launch_parents(const BfsParams& p, uint32_t sigma, const int32_t* levels, int32_t* parents,
+                          hipStream_t stream);
+
+}  // namespace blest

@@ -1,0 +1,258 @@
+"""CPU tests of libblest's host side through the C-ABI: exported symbols, argument
+and graph validation, and parity of the host-side hot-path steps with the oracle -
+BVSS construction (Section 2.1), Algorithm 1, RCM, the social-like test, the
+statistics of Sections 2.2/2.2.1 and the static eager/lazy rule.  Handles are built
+host-only (device = -1), so no GPU is touched."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import inputs
+import paper_2512_21967_amd as blest
+from oracle import bvss as obvss
+from oracle import reorder as oreorder
+from tests import families
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def host_graph(g, **kw):
+    kw.setdefault("device", -1)
+    return blest.Graph(g, **kw)
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "blest.h")).read()
+    declared = set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(blest_\w+)\s*\(", header, re.M))
+    assert "blest_build" in declared and "blest_bfs_multi" in declared
+    L = ctypes.CDLL(blest.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(L, name), f"{name} missing from libblest.so"
+    assert declared == set(blest.EXPORTED_SYMBOLS)
+
+
+def test_status_strings():
+    L = blest.lib()
+    for code in range(9):
+        assert L.blest_status_string(code)
+
+
+def raw_build(n, rp, col, opt=None):
+    L = blest.lib()
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(rp, np.uint32)
+    col = np.ascontiguousarray(col if len(col) else [0], np.uint32)
+    o = opt or blest.default_options()
+    if opt is None:
+        o.device = -1
+    rc = L.blest_build(n, int(rp[-1]) if len(rp) else 0, blest._p32(rp), blest._p32(col), ctypes.byref(o),
+                       ctypes.byref(h))
+    if rc == 0:
+        L.blest_destroy(h)
+    return rc
+
+
+def test_graph_validation_errors():
+    assert raw_build(3, [0, 1, 2, 2], [1, 2]) == 0
+    assert raw_build(3, [0, 2, 1, 2], [1, 2]) == 2            # row_ptr not monotone
+    assert raw_build(3, [0, 1, 2, 2], [1, 3]) == 2            # column out of range
+    assert raw_build(3, [1, 1, 2, 2], [1, 2]) == 2            # row_ptr[0] != 0
+    L = blest.lib()
+    h = ctypes.c_void_p()
+    rp = np.array([0, 1], np.uint32)
+    col = np.array([0], np.uint32)
+    o = blest.default_options()
+    o.device = -1
+    assert L.blest_build(0, 0, blest._p32(rp), blest._p32(col), ctypes.byref(o), ctypes.byref(h)) == 1
+    assert L.blest_build(1, 2 ** 32, blest._p32(rp), blest._p32(col), ctypes.byref(o), ctypes.byref(h)) == 3
+    assert L.blest_build(1, 0, None, None, ctypes.byref(o), ctypes.byref(h)) == 1
+    assert L.blest_build(1, 0, blest._p32(rp), blest._p32(col), ctypes.byref(o), None) == 1
+    for field, bad in (("sigma", 12), ("slots", 3), ("window", 12), ("reorder", 9), ("update", -1), ("block", 100)):
+        o = blest.default_options()
+        o.device = -1
+        setattr(o, field, bad)
+        assert raw_build(2, [0, 1, 1], [1], o) == 1, field
+
+
+def test_self_loops_and_duplicates_dropped():
+    g = host_graph(types_graph(4, [0, 2, 4, 4, 4], [0, 1, 1, 1]), reorder="none")
+    assert g.stats()["m"] == 1
+
+
+def types_graph(n, rp, col):
+    class G:
+        pass
+    x = G()
+    x.n, x.row_ptr, x.col = n, np.array(rp, np.uint32), np.array(col, np.uint32)
+    return x
+
+
+def test_bfs_calls_on_host_only_handle():
+    gr, _ = families.path(10)
+    g = host_graph(gr)
+    L = blest.lib()
+    assert L.blest_bfs(g.handle, 10, ctypes.c_void_p(1), None, None) == 1     # source out of range
+    assert L.blest_bfs(g.handle, 0, None, None, None) == 1                    # no output
+    assert L.blest_bfs(g.handle, 0, ctypes.c_void_p(1), None, None) == 7      # host-only handle
+    src = np.array([0, 1], np.uint32)
+    assert L.blest_bfs_multi(g.handle, blest._p32(src), 0, ctypes.c_void_p(1), None) == 1
+    assert L.blest_bfs_multi(g.handle, blest._p32(src), 65, ctypes.c_void_p(1), None) == 1
+    bad = np.array([0, 10], np.uint32)
+    assert L.blest_bfs_multi(g.handle, blest._p32(bad), 2, ctypes.c_void_p(1), None) == 1
+    assert L.blest_bfs_multi(g.handle, blest._p32(src), 2, ctypes.c_void_p(1), None) == 7
+    hs = (ctypes.c_void_p * 1)(g.handle.value)
+    outs = (ctypes.c_void_p * 1)(1)
+    one = np.array([0], np.uint32)
+    assert L.blest_bfs_many(hs, blest._p32(one), 1, outs, None) == 7
+    assert L.blest_bfs_many(hs, blest._p32(one), 0, outs, None) == 1
+
+
+# ---------------------------------------------------------------------------
+# BVSS structure parity with the oracle
+# ---------------------------------------------------------------------------
+
+def relabelled(gr, new_id):
+    return inputs.relabel(gr, new_id) if not np.array_equal(new_id, np.arange(gr.n)) else gr
+
+
+def check_bvss_against_oracle(gr, g, sigma, slots):
+    new_id = g.export("new_id")
+    assert sorted(new_id.tolist()) == list(range(gr.n))
+    h = relabelled(gr, new_id)
+    sid, row, mask = obvss.slices(h, sigma)
+    n_sets = obvss.num_slice_sets(h.n, sigma)
+    tau = 64 * slots
+    part = obvss.vss_partition(sid, row, mask, n_sets, tau)
+    rp = g.export("real_ptrs")
+    v2r = g.export("virtual_to_real")
+    beg = g.export("vss_begin")
+    rows = g.export("row_ids")
+    masks = g.export("masks")
+    mb = sigma // 8
+    mvals = np.zeros(len(rows), np.uint64)
+    for b in range(mb):
+        mvals |= masks[b::mb].astype(np.uint64) << np.uint64(8 * b)
+    np.testing.assert_array_equal(rp, part["realPtrs"])
+    np.testing.assert_array_equal(v2r, part["virtualToReal"])
+    assert beg[0] == 0 and beg[-1] == len(rows) == len(sid)
+    for v, (r, m) in enumerate(part["groups"]):
+        np.testing.assert_array_equal(rows[beg[v]:beg[v + 1]], r)
+        np.testing.assert_array_equal(mvals[beg[v]:beg[v + 1]], m)
+    st = g.stats()
+    assert st["num_slices"] == len(sid) and st["num_vss"] == len(v2r) and st["tau"] == tau
+    assert st["compression"] == pytest.approx(obvss.compression_ratio(h.nnz, len(sid), sigma))
+    paper_groups = obvss.vss_partition(sid, row, mask, n_sets, 32 * (32 // sigma))["groups"]
+    assert st["u_div_paper"] == pytest.approx(obvss.update_divergence(paper_groups, 32), rel=1e-9, abs=1e-9)
+    assert st["u_div_native"] == pytest.approx(obvss.update_divergence(part["groups"], 64), rel=1e-9, abs=1e-9)
+    assert st["bvss_bytes_table3"] == obvss.bvss_bytes_table3(len(sid), len(v2r), n_sets, sigma)
+
+
+@pytest.mark.parametrize("sigma,slots", [(8, 1), (8, 4), (16, 2), (32, 1), (8, 8)])
+def test_bvss_matches_oracle_rmat(sigma, slots):
+    gr = inputs.rmat_workload(11, 16, seed=sigma + slots, permute_seed=2)
+    g = host_graph(gr, sigma=sigma, slots=slots, reorder="none")
+    check_bvss_against_oracle(gr, g, sigma, slots)
+
+
+def test_bvss_matches_oracle_directed_and_ragged():
+    rng = np.random.default_rng(3)
+    for n in (1, 7, 63, 65, 200, 1001):
+        m = n * 5
+        gr = inputs.from_arcs(n, rng.integers(0, n, m), rng.integers(0, n, m), False)
+        g = host_graph(gr, sigma=8, slots=1, reorder="none")
+        check_bvss_against_oracle(gr, g, 8, 1)
+
+
+@pytest.mark.parametrize("reorder", ["compression", "bandwidth"])
+def test_bvss_matches_oracle_after_reordering(reorder):
+    gr = inputs.rmat_workload(10, 8, seed=5, permute_seed=1) if reorder == "compression" else \
+        inputs.grid_workload(40, 0.9, seed=2, permute_seed=6)
+    g = host_graph(gr, sigma=8, slots=2, reorder=reorder, window=256)
+    check_bvss_against_oracle(gr, g, 8, 2)
+
+
+# ---------------------------------------------------------------------------
+# Orderings and the static policy
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_jaccard_windows_matches_oracle(seed):
+    rng = np.random.default_rng(seed)
+    sigma = [8, 16, 8, 32, 8, 8][seed]
+    w = sigma * int(rng.integers(2, 9))
+    if seed % 2 == 0:
+        gr = inputs.rmat_workload(8, 8, seed=seed, permute_seed=seed + 10)
+    else:
+        n = int(rng.integers(20, 300))
+        m = n * int(rng.integers(1, 6))
+        gr = inputs.from_arcs(n, rng.integers(0, n, m), rng.integers(0, n, m), bool(seed % 3))
+    g = host_graph(gr, sigma=sigma, window=w, reorder="compression")
+    np.testing.assert_array_equal(g.export("new_id"), oreorder.jaccard_with_windows(gr, sigma, w))
+
+
+def test_jaccard_windows_matches_oracle_hand_cases():
+    for adj, n, sigma, w in (({0: [4, 5], 1: [6], 2: [4], 3: [5]}, 8, 8, 8),
+                             ({0: [4], 1: [5, 6], 2: [4, 5, 6], 3: [4, 8, 9, 10]}, 16, 8, 8)):
+        src = [u for u, vs in adj.items() for _ in vs]
+        dst = [v for vs in adj.values() for v in vs]
+        gr = inputs.from_arcs(n, src, dst, False)
+        g = host_graph(gr, sigma=sigma, window=w, reorder="compression")
+        np.testing.assert_array_equal(g.export("new_id"), oreorder.jaccard_with_windows(gr, sigma, w))
+
+
+@pytest.mark.parametrize("case", ["grid", "rmat", "union", "directed", "isolated"])
+def test_rcm_matches_oracle(case):
+    rng = np.random.default_rng(1)
+    if case == "grid":
+        gr = inputs.grid_workload(23, 0.9, seed=5, permute_seed=2)
+    elif case == "rmat":
+        gr = inputs.rmat_workload(9, 4, seed=3, permute_seed=4)
+    elif case == "union":
+        gr = inputs.relabel(families.disjoint_union_paths(9, 14)[0], inputs.permutation(23, 3))
+    elif case == "directed":
+        gr = inputs.from_arcs(150, rng.integers(0, 150, 300), rng.integers(0, 150, 300), False)
+    else:
+        gr = inputs.from_arcs(30, [1, 5, 9], [2, 6, 10], True)
+    g = host_graph(gr, reorder="bandwidth")
+    np.testing.assert_array_equal(g.export("new_id"), oreorder.rcm(gr))
+
+
+def test_social_like_and_auto_policy():
+    cases = [inputs.rmat(12, 16, seed=1), inputs.grid(50, 50, 0.9, seed=1), families.star(300)[0],
+             families.path(300)[0], inputs.from_arcs(20, [], [], False)]
+    for gr in cases:
+        g = host_graph(gr, window=64)
+        st = g.stats()
+        social = oreorder.is_social_like(gr)
+        assert bool(st["social_like"]) == social
+        assert st["reorder_used"] == ("compression" if social else "bandwidth")
+        lazy = social and st["u_div_paper"] > 25000
+        assert st["update_used"] == ("lazy" if lazy else "eager")
+
+
+def test_auto_update_rule_threshold():
+    # Section 4: a graph smaller than ~50K vertices cannot exceed the 25,000 threshold
+    g = host_graph(inputs.rmat_workload(12, 16, seed=1, permute_seed=3), reorder="none")
+    assert g.stats()["update_used"] == "eager"
+    # random labels at scale 19 spread each VSS column over ~29K IDs: lazy
+    g = host_graph(inputs.rmat_workload(19, 16, seed=1, permute_seed=3), reorder="none")
+    st = g.stats()
+    assert st["u_div_paper"] > 25000 and st["update_used"] == "lazy"
+
+
+def test_footprint_and_model_bytes():
+    gr = inputs.rmat(10, 8, seed=2)
+    g = host_graph(gr, reorder="none")
+    f0, f1, f8, f64 = (g.footprint(k) for k in (0, 1, 8, 64))
+    assert f0 == g.stats()["bvss_device_bytes"] and 0 < f1 < f8 < f64
+    lv = np.full(gr.n, -1, np.int32)
+    lv[0] = 0
+    b_one = g.model_bytes(lv)
+    lv[:] = 0
+    b_all = g.model_bytes(lv)
+    assert 4 * gr.n < b_one < b_all

@@ -1,0 +1,150 @@
+"""GPU parity of the single-source BFS (``blest_bfs``) with the oracle, through the
+C-ABI.  Levels must be bit-exact; parents must pass the Graph500-style checks.
+Covers both update schemes (Algorithm 2 eager, Algorithm 3 lazy), every slice width
+and slot count, the two orderings, tiny closed-form families, ragged and degenerate
+inputs, a hub whose slice set spans many VSSs, directed graphs (pull direction),
+and repeated runs (no races)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from tests import families
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+blest = pytest.importorskip("paper_2512_21967_amd")
+
+
+def run(g, s, parents=False):
+    out = g.bfs(int(s), parents=parents)
+    torch.cuda.synchronize()
+    if parents:
+        return out[0].cpu().numpy(), out[1].cpu().numpy()
+    return out.cpu().numpy()
+
+
+def check_sources(gr, g, srcs, with_parents=False):
+    for s in srcs:
+        s = int(s)
+        want = oracle.bfs(gr, s)
+        if with_parents:
+            got, par = run(g, s, parents=True)
+            np.testing.assert_array_equal(got, want, err_msg=f"{gr.name or 'graph'} source {s}")
+            assert oracle.validate_tree(gr, s, want, par) == 0, f"bad parents from source {s}"
+        else:
+            got = run(g, s)
+            np.testing.assert_array_equal(got, want, err_msg=f"{gr.name or 'graph'} source {s}")
+
+
+@pytest.mark.parametrize("update", ["eager", "lazy"])
+@pytest.mark.parametrize("name", sorted(families.ALL_FAMILIES))
+def test_closed_form_families_every_source(name, update):
+    gr, lv = families.ALL_FAMILIES[name]()
+    g = blest.Graph(gr, update=update, reorder="none")
+    for s in range(gr.n):
+        np.testing.assert_array_equal(run(g, s), lv(s), err_msg=f"{name} source {s} ({update})")
+
+
+@pytest.mark.parametrize("update", ["eager", "lazy"])
+@pytest.mark.parametrize("sigma,slots", [(8, 1), (8, 2), (8, 4), (8, 8), (16, 4), (32, 2)])
+def test_rmat_widths_and_slots(sigma, slots, update):
+    gr = inputs.rmat_workload(13, 16, seed=sigma * 10 + slots, permute_seed=1)
+    g = blest.Graph(gr, sigma=sigma, slots=slots, update=update, reorder="none")
+    check_sources(gr, g, inputs.sources(gr, seed=3, k=4))
+
+
+@pytest.mark.parametrize("update", ["eager", "lazy"])
+@pytest.mark.parametrize("reorder", ["compression", "bandwidth"])
+def test_reordered_graphs_map_back(reorder, update):
+    if reorder == "compression":
+        gr = inputs.rmat_workload(12, 16, seed=4, permute_seed=2)
+        kw = dict(window=1024)
+    else:
+        gr = inputs.grid_workload(96, 0.9, seed=2, permute_seed=5)
+        kw = {}
+    g = blest.Graph(gr, reorder=reorder, update=update, **kw)
+    check_sources(gr, g, inputs.sources(gr, seed=8, k=4))
+
+
+@pytest.mark.parametrize("update", ["eager", "lazy"])
+def test_parents_pass_graph500_checks(update):
+    gr = inputs.rmat_workload(12, 16, seed=6, permute_seed=3)
+    g = blest.Graph(gr, update=update, reorder="compression", window=512)
+    check_sources(gr, g, inputs.sources(gr, seed=2, k=3), with_parents=True)
+    grid = inputs.grid_workload(40, 0.9, seed=1, permute_seed=2)
+    g = blest.Graph(grid, update=update)
+    check_sources(grid, g, inputs.sources(grid, seed=2, k=2), with_parents=True)
+
+
+@pytest.mark.parametrize("update", ["eager", "lazy"])
+def test_directed_graphs_follow_out_edges(update):
+    rng = np.random.default_rng(11)
+    for n in (2, 31, 33, 257, 3000):
+        m = 3 * n
+        gr = inputs.from_arcs(n, rng.integers(0, n, m), rng.integers(0, n, m), False)
+        g = blest.Graph(gr, update=update, reorder="none", slots=1)
+        check_sources(gr, g, range(0, n, max(1, n // 5)))
+
+
+@pytest.mark.parametrize("update", ["eager", "lazy"])
+def test_degenerate_inputs(update):
+    # one vertex, no arcs
+    one = inputs.from_arcs(1, [], [], False)
+    g = blest.Graph(one, update=update, reorder="none")
+    np.testing.assert_array_equal(run(g, 0), [0])
+    # isolated source inside a set that has VSSs
+    gr = inputs.from_arcs(40, [1, 2, 3, 9], [2, 3, 4, 10], True)
+    g = blest.Graph(gr, update=update, reorder="none")
+    for s in (0, 1, 5, 9, 39):
+        np.testing.assert_array_equal(run(g, s), oracle.bfs(gr, s))
+    # hub: the centre's slice set spans many VSSs
+    star, lv = families.star(20000)
+    g = blest.Graph(star, update=update, reorder="none", slots=1)
+    for s in (0, 1, 19999):
+        np.testing.assert_array_equal(run(g, s), lv(s))
+
+
+def test_repeated_runs_identical():
+    gr = inputs.rmat_workload(14, 16, seed=9, permute_seed=4)
+    for update in ("eager", "lazy"):
+        g = blest.Graph(gr, update=update, reorder="none")
+        s = int(inputs.sources(gr, seed=1, k=1)[0])
+        want = oracle.bfs(gr, s)
+        for _ in range(20):
+            np.testing.assert_array_equal(run(g, s), want)
+
+
+def test_launch_shapes():
+    gr = inputs.rmat_workload(12, 16, seed=2, permute_seed=7)
+    srcs = inputs.sources(gr, seed=5, k=2)
+    for block, per_cu in ((64, 1), (256, 1), (1024, 1), (512, 4)):
+        for update in ("eager", "lazy"):
+            g = blest.Graph(gr, update=update, reorder="none", block=block, blocks_per_cu=per_cu)
+            check_sources(gr, g, srcs)
+
+
+def test_streams_and_async():
+    gr = inputs.rmat_workload(12, 16, seed=3, permute_seed=1)
+    g = blest.Graph(gr, reorder="none")
+    srcs = [int(x) for x in inputs.sources(gr, seed=4, k=6)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    outs = []
+    for i, s in enumerate(srcs):
+        st = streams[i % 3]
+        with torch.cuda.stream(st):
+            outs.append(g.bfs(s, stream=st))
+    torch.cuda.synchronize()
+    for s, o in zip(srcs, outs):
+        np.testing.assert_array_equal(o.cpu().numpy(), oracle.bfs(gr, s))
+
+
+def test_full_size_s16_config():
+    """R-MAT scale 16, edge factor 16, plain ordering (the small benchmark config)."""
+    gr = inputs.rmat_workload(16, 16, seed=1)
+    for update in ("eager", "lazy"):
+        g = blest.Graph(gr, reorder="none", update=update)
+        check_sources(gr, g, inputs.sources(gr, seed=1, k=3))
