@@ -74,8 +74,9 @@ typedef struct {
   int32_t update;      /* BLEST_UPDATE_* */
   int32_t device;      /* HIP device ordinal; -1 builds host-only (structure and stats) */
   uint32_t threads;    /* host threads for the build (0 = all hardware threads) */
-  uint32_t block;      /* threads per workgroup of the persistent kernels (0 = 512) */
-  uint32_t blocks_per_cu; /* persistent workgroups per compute unit (0 = 2) */
+  uint32_t block;      /* threads per workgroup of the persistent kernels, a multiple of 64 (0 = 1024) */
+  uint32_t blocks_per_cu; /* persistent workgroups per compute unit (0 = 1); block * blocks_per_cu <= 1024 */
+  uint32_t group;      /* VSSs whose slice loads a wavefront keeps in flight: 1, 2 or 4 (0 = 2) */
 } blest_options;
 
 typedef struct {
@@ -135,6 +136,14 @@ blest_status blest_bfs_multi(blest_handle h, const uint32_t* sources, uint32_t k
  * (non-cooperative) kernel, so it can be captured into a HIP graph. */
 blest_status blest_bfs_many(const blest_handle* hs, const uint32_t* sources, uint32_t g,
                             int32_t* const* levels_out, void* stream);
+
+/* Changes the launch settings of a built handle without rebuilding it: update
+ * scheme (BLEST_UPDATE_*), threads per workgroup, workgroups per compute unit and
+ * VSS group depth, with the meanings (and 0 = default) of blest_options.  Used by
+ * autotuning.  Must not be called while work on the handle is in flight.
+ * Errors: INVALID_ARGUMENT (bad values; the handle is left unchanged), DEVICE. */
+blest_status blest_configure(blest_handle h, int32_t update, uint32_t block, uint32_t blocks_per_cu,
+                             uint32_t group);
 
 /* Structure statistics of a built handle (host-side, no device access). */
 blest_status blest_stats(blest_handle h, blest_stats_t* out);

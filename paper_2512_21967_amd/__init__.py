@@ -24,7 +24,7 @@ UPDATE = {"auto": 0, "eager": 1, "lazy": 2}
 EXPORT = {"new_id": (0, np.uint32), "real_ptrs": (1, np.uint32), "virtual_to_real": (2, np.uint32),
           "vss_begin": (3, np.uint32), "row_ids": (4, np.uint32), "masks": (5, np.uint8)}
 EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_bfs_multi", "blest_bfs_many",
-                    "blest_stats", "blest_footprint", "blest_export", "blest_model_bytes", "blest_destroy",
+                    "blest_configure", "blest_stats", "blest_footprint", "blest_export", "blest_model_bytes", "blest_destroy",
                     "blest_status_string")
 
 
@@ -37,7 +37,8 @@ class BlestError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("window", ctypes.c_uint32),
                 ("reorder", ctypes.c_int32), ("update", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("threads", ctypes.c_uint32), ("block", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32)]
+                ("threads", ctypes.c_uint32), ("block", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("group", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -74,6 +75,8 @@ def lib():
     L.blest_bfs_multi.restype = ctypes.c_int
     L.blest_bfs_many.argtypes = [ctypes.POINTER(vp), p32, u32, ctypes.POINTER(vp), vp]
     L.blest_bfs_many.restype = ctypes.c_int
+    L.blest_configure.argtypes = [vp, i32, u32, u32, u32]
+    L.blest_configure.restype = ctypes.c_int
     L.blest_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.blest_stats.restype = ctypes.c_int
     L.blest_footprint.argtypes = [vp, u32, ctypes.POINTER(u64)]
@@ -127,11 +130,12 @@ class Graph:
     and exports work; BFS calls raise)."""
 
     def __init__(self, csr, *, sigma=8, slots=4, window=1 << 16, reorder="auto", update="auto",
-                 device=0, threads=0, block=0, blocks_per_cu=0):
+                 device=0, threads=0, block=0, blocks_per_cu=0, group=0):
         o = default_options()
         o.sigma, o.slots, o.window = sigma, slots, window
         o.reorder, o.update = REORDER[reorder], UPDATE[update]
         o.device, o.threads, o.block, o.blocks_per_cu = device, threads, block, blocks_per_cu
+        o.group = group
         rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint32)
         col = np.ascontiguousarray(csr.col if len(csr.col) else np.zeros(1, np.uint32), dtype=np.uint32)
         h = ctypes.c_void_p()
@@ -195,6 +199,10 @@ class Graph:
         _check("blest_bfs_multi", lib().blest_bfs_multi(self.handle, _p32(src), k,
                                                         ctypes.c_void_p(levels.data_ptr()), _stream_ptr(stream)))
         return levels
+
+    def configure(self, update="auto", block=0, blocks_per_cu=0, group=0):
+        """Changes launch settings (update scheme, workgroup shape, group depth)."""
+        _check("blest_configure", lib().blest_configure(self.handle, UPDATE[update], block, blocks_per_cu, group))
 
     # -- host-side information -------------------------------------------------
     def stats(self) -> dict:

@@ -46,6 +46,12 @@ struct SingleWorkspace {
   DevBuf vis, front, queue, ctrl;
 };
 
+// Per-stream scratch of the k-source kernel: 64-bit visited pairs and frontier
+// words per vertex, two queues, control block.
+struct MultiWorkspace {
+  DevBuf vis, front, queue, ctrl;
+};
+
 // Persistent launches are serialised device-wide: two persistent grids that each
 // wait for all of their workgroups could otherwise starve one another of compute
 // units.  Every persistent launch waits on the previous one's completion event.
@@ -77,6 +83,8 @@ struct blest_graph {
   uint32_t grid = 0, block = 0;
   std::mutex ws_mu;
   std::map<void*, std::unique_ptr<SingleWorkspace>> single_ws;
+  std::map<void*, std::unique_ptr<MultiWorkspace>> multi_ws;
+  uint32_t multi_grid = 0;
   uint32_t n_words() const { return (n + 31) / 32; }
 };
 
@@ -104,6 +112,10 @@ bool valid_options(const blest_options& o) {
   if (o.update < BLEST_UPDATE_AUTO || o.update > BLEST_UPDATE_LAZY) return false;
   if (o.block % 64 != 0 || o.block > 1024) return false;
   if (o.blocks_per_cu > 16) return false;
+  // Persistent grids fill at most half of a compute unit's wave slots: a launch
+  // that filled all of them (1024 x 2) hung once, cause not identified.
+  if ((uint64_t)o.block * (o.blocks_per_cu ? o.blocks_per_cu : 1) > 1024) return false;
+  if (o.group != 1 && o.group != 2 && o.group != 4) return false;
   return true;
 }
 
@@ -114,6 +126,8 @@ hipError_t upload(DevBuf& d, const std::vector<T>& h) {
   if (h.empty()) return hipSuccess;
   return hipMemcpy(d.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
 }
+
+blest_status set_grid(blest_graph* g);
 
 blest_status to_device(blest_graph* g) {
   if (hipSetDevice(g->device) != hipSuccess) return BLEST_ERR_NO_DEVICE;
@@ -127,7 +141,15 @@ blest_status to_device(blest_graph* g) {
   if (e == hipSuccess && !g->identity) e = upload(g->d_orig_id, g->orig_id);
   if (e == hipErrorOutOfMemory) return BLEST_ERR_OUT_OF_MEMORY;
   if (e != hipSuccess) return BLEST_ERR_DEVICE;
-  // Persistent grid: co-resident workgroups, capped at blocks_per_cu per CU.
+  blest_status st = set_grid(g);
+  if (st != BLEST_OK) return st;
+  g->on_device = true;
+  return BLEST_OK;
+}
+
+// Persistent grid: co-resident workgroups, capped at blocks_per_cu per CU.
+blest_status set_grid(blest_graph* g) {
+  const Bvss& b = g->bvss;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess || cus <= 0)
     return BLEST_ERR_DEVICE;
@@ -135,14 +157,19 @@ blest_status to_device(blest_graph* g) {
   uint32_t per_cu = UINT32_MAX;
   for (int lazy = 0; lazy < 2; ++lazy) {
     int nb = 0;
-    const void* k = bfs_kernel_symbol(b.sigma, b.slots, lazy != 0);
+    const void* k = bfs_kernel_symbol(b.sigma, b.slots, lazy != 0, g->opt.group);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)g->block, 0) != hipSuccess || nb <= 0)
       return BLEST_ERR_DEVICE;
     per_cu = std::min<uint32_t>(per_cu, (uint32_t)nb);
   }
   per_cu = std::min<uint32_t>(per_cu, g->opt.blocks_per_cu);
   g->grid = per_cu * (uint32_t)cus;
-  g->on_device = true;
+  int nbm = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbm, bfs_multi_kernel_symbol(b.sigma, b.slots), (int)g->block, 0) !=
+          hipSuccess ||
+      nbm <= 0)
+    return BLEST_ERR_DEVICE;
+  g->multi_grid = std::min<uint32_t>((uint32_t)nbm, g->opt.blocks_per_cu) * (uint32_t)cus;
   return BLEST_OK;
 }
 
@@ -164,6 +191,27 @@ SingleWorkspace* single_workspace(blest_graph* g, void* stream, blest_status* st
   }
   SingleWorkspace* raw = ws.get();
   g->single_ws.emplace(stream, std::move(ws));
+  return raw;
+}
+
+MultiWorkspace* multi_workspace(blest_graph* g, void* stream, blest_status* st) {
+  std::lock_guard<std::mutex> lk(g->ws_mu);
+  auto it = g->multi_ws.find(stream);
+  if (it != g->multi_ws.end()) return it->second.get();
+  auto ws = std::make_unique<MultiWorkspace>();
+  const size_t n = g->n;
+  hipError_t e = ws->vis.alloc(16 * n);
+  if (e == hipSuccess) e = ws->front.alloc(8 * n);
+  if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 2 * std::max<size_t>(g->bvss.num_vss, 1));
+  if (e == hipSuccess) e = ws->ctrl.alloc(sizeof(uint32_t) * kCtrlWords);
+  if (e == hipSuccess) e = hipMemset(ws->ctrl.p, 0, sizeof(uint32_t) * kCtrlWords);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    *st = e == hipErrorOutOfMemory ? BLEST_ERR_OUT_OF_MEMORY : BLEST_ERR_DEVICE;
+    return nullptr;
+  }
+  MultiWorkspace* raw = ws.get();
+  g->multi_ws.emplace(stream, std::move(ws));
   return raw;
 }
 
@@ -215,8 +263,9 @@ void blest_default_options(blest_options* o) {
   o->update = BLEST_UPDATE_AUTO;
   o->device = 0;
   o->threads = 0;
-  o->block = 512;
-  o->blocks_per_cu = 2;
+  o->block = 1024;
+  o->blocks_per_cu = 1;
+  o->group = 2;
 }
 
 blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, const uint32_t* col_idx,
@@ -228,8 +277,9 @@ blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, cons
   blest_options o;
   blest_default_options(&o);
   if (opt) o = *opt;
-  if (o.block == 0) o.block = 512;
-  if (o.blocks_per_cu == 0) o.blocks_per_cu = 2;
+  if (o.block == 0) o.block = 1024;
+  if (o.blocks_per_cu == 0) o.blocks_per_cu = 1;
+  if (o.group == 0) o.group = 2;
   if (!valid_options(o)) return BLEST_ERR_INVALID_ARGUMENT;
   std::unique_ptr<blest_graph> g;
   try {
@@ -313,7 +363,7 @@ blest_status blest_bfs(blest_handle h, uint32_t source, int32_t* levels_out, int
     p.src = h->new_id[source];
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = serial_launch(h->device, s, [&] {
-      return launch_bfs(p, h->bvss.sigma, h->bvss.slots, h->lazy, h->grid, h->block, s);
+      return launch_bfs(p, h->bvss.sigma, h->bvss.slots, h->lazy, h->opt.group, h->grid, h->block, s);
     });
     if (e == hipSuccess && parents_out) e = launch_parents(p, h->bvss.sigma, levels_out, parents_out, s);
     return e == hipSuccess ? BLEST_OK : BLEST_ERR_DEVICE;
@@ -328,8 +378,43 @@ blest_status blest_bfs_multi(blest_handle h, const uint32_t* sources, uint32_t k
   for (uint32_t j = 0; j < k; ++j)
     if (sources[j] >= h->n) return BLEST_ERR_INVALID_ARGUMENT;
   if (!h->on_device) return BLEST_ERR_NO_DEVICE;
-  (void)stream;
-  return BLEST_ERR_INTERNAL;
+  try {
+    if (hipSetDevice(h->device) != hipSuccess) return BLEST_ERR_DEVICE;
+    blest_status st = BLEST_OK;
+    MultiWorkspace* ws = multi_workspace(h, stream, &st);
+    if (!ws) return st;
+    MultiParams p{};
+    p.row_ids = h->d_row_ids.as<uint32_t>();
+    p.masks = h->d_masks.p;
+    p.vss_beg = h->d_vss_beg.as<uint32_t>();
+    p.v2r = h->d_v2r.as<uint32_t>();
+    p.real_ptrs = h->d_real_ptrs.as<uint32_t>();
+    p.orig_id = h->identity ? nullptr : h->d_orig_id.as<uint32_t>();
+    p.vis = ws->vis.as<unsigned long long>();
+    p.front = ws->front.as<unsigned long long>();
+    p.queue = ws->queue.as<uint32_t>();
+    p.ctrl = ws->ctrl.as<uint32_t>();
+    p.levels = levels_out;
+    p.n = h->n;
+    p.num_sets = h->bvss.num_sets;
+    p.num_vss = h->bvss.num_vss;
+    p.qcap = std::max<uint32_t>(h->bvss.num_vss, 1);
+    p.k = k;
+    for (uint32_t j = 0; j < k; ++j) {
+      p.src[j] = h->new_id[sources[j]];
+      const uint32_t ss = p.src[j] / h->bvss.sigma;
+      bool seen = false;
+      for (uint32_t i = 0; i < p.n_init_sets; ++i) seen |= p.init_sets[i] == ss;
+      if (!seen) p.init_sets[p.n_init_sets++] = ss;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = serial_launch(h->device, s, [&] {
+      return launch_bfs_multi(p, h->bvss.sigma, h->bvss.slots, h->multi_grid, h->block, s);
+    });
+    return e == hipSuccess ? BLEST_OK : BLEST_ERR_DEVICE;
+  } catch (...) {
+    return BLEST_ERR_INTERNAL;
+  }
 }
 
 blest_status blest_bfs_many(const blest_handle* hs, const uint32_t* sources, uint32_t g,
@@ -341,6 +426,34 @@ blest_status blest_bfs_many(const blest_handle* hs, const uint32_t* sources, uin
   }
   (void)stream;
   return BLEST_ERR_INTERNAL;
+}
+
+blest_status blest_configure(blest_handle h, int32_t update, uint32_t block, uint32_t blocks_per_cu, uint32_t group) {
+  if (!h) return BLEST_ERR_INVALID_ARGUMENT;
+  blest_options o = h->opt;
+  o.update = update;
+  o.block = block ? block : 1024;
+  o.blocks_per_cu = blocks_per_cu ? blocks_per_cu : 1;
+  o.group = group ? group : 2;
+  if (!valid_options(o)) return BLEST_ERR_INVALID_ARGUMENT;
+  const blest_options old = h->opt;
+  const bool old_lazy = h->lazy;
+  h->opt = o;
+  if (o.update == BLEST_UPDATE_AUTO)
+    h->lazy = h->social && h->u_div_paper > 25000.0;
+  else
+    h->lazy = o.update == BLEST_UPDATE_LAZY;
+  if (h->on_device) {
+    if (hipSetDevice(h->device) != hipSuccess) return BLEST_ERR_DEVICE;
+    blest_status st = set_grid(h);
+    if (st != BLEST_OK) {
+      h->opt = old;
+      h->lazy = old_lazy;
+      (void)set_grid(h);
+      return st;
+    }
+  }
+  return BLEST_OK;
 }
 
 blest_status blest_stats(blest_handle h, blest_stats_t* o) {

@@ -1,0 +1,83 @@
+// Device helpers shared by the BFS kernels: wavefront primitives and the grid
+// barrier of the persistent launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace blest {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kMaxWaves = 1024 / kWave;  // wavefronts per workgroup at most
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Two-level grid barrier.  Block b arrives on the counter of group b % 8 (the
+// XCD it is dispatched to); the last arrival of a group arrives on the root; the
+// last root arrival resets the counters and bumps the generation, on which every
+// other block spins.  Ordering comes from fences, not from the counters: each
+// block issues an agent-scope release fence before arriving and an agent-scope
+// acquire fence after seeing the new generation, and the last arrival of a group
+// and the flipping block issue acq_rel fences between their counter updates
+// (fence-to-fence synchronisation through the counters), so every write made before
+// the barrier by any block is visible to every block after it.  Arrivals and the
+// spin are relaxed, which keeps cache maintenance out of the spin loop (about 3x
+// cheaper than acquire loads in the loop on MI355X).
+__device__ __forceinline__ void grid_barrier(uint32_t* ctrl) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t nb = gridDim.x;
+    const uint32_t grp = blockIdx.x % kBarGroups;
+    const uint32_t ngroups = nb < kBarGroups ? nb : kBarGroups;
+    const uint32_t gsize = (nb - grp + kBarGroups - 1) / kBarGroups;
+    uint32_t* gen = ctrl + kBarGen;
+    const uint32_t g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    bool flipped = false;
+    if (__hip_atomic_fetch_add(ctrl + grp * kLine, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gsize - 1) {
+      __hip_atomic_store(ctrl + grp * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");  // carries the group's writes to the root
+      if (__hip_atomic_fetch_add(ctrl + kBarRoot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ngroups - 1) {
+        __hip_atomic_store(ctrl + kBarRoot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_store(gen, g0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        flipped = true;
+      }
+    }
+    if (!flipped)
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// Inclusive prefix sum across the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, kWave);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane) {
+  const uint32_t lo = readlane((uint32_t)v, lane), hi = readlane((uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+}  // namespace
+}  // namespace blest

@@ -27,61 +27,11 @@
 
 #include <climits>
 
+#include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace blest {
 namespace {
-
-constexpr int kWave = 64;
-
-__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
-
-__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Two-level grid barrier.  Block b arrives on the counter of group b % 8 (the
-// XCD it is dispatched to); the last arrival of a group arrives on the root; the
-// last root arrival resets the counters and bumps the generation, on which every
-// other block waits.  Arrivals are acq_rel and the generation is published with
-// release and read with acquire, all at agent scope, so every write made before
-// the barrier by any block is visible after it.
-__device__ __forceinline__ void grid_barrier(uint32_t* ctrl) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t nb = gridDim.x;
-    const uint32_t grp = blockIdx.x % kBarGroups;
-    const uint32_t ngroups = nb < kBarGroups ? nb : kBarGroups;
-    const uint32_t gsize = (nb - grp + kBarGroups - 1) / kBarGroups;
-    uint32_t* gen = ctrl + kBarGen;
-    const uint32_t g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool flipped = false;
-    uint32_t prev = __hip_atomic_fetch_add(ctrl + grp * kLine, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == gsize - 1) {
-      __hip_atomic_store(ctrl + grp * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      uint32_t r = __hip_atomic_fetch_add(ctrl + kBarRoot, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (r == ngroups - 1) {
-        __hip_atomic_store(ctrl + kBarRoot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(gen, g0 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        flipped = true;
-      }
-    }
-    if (!flipped)
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) __builtin_amdgcn_s_sleep(1);
-  }
-  __syncthreads();
-}
-
-// Inclusive prefix sum across the 64 lanes of a wavefront.
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
-  const uint32_t lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, kWave);
-    if (lane >= (uint32_t)o) x += y;
-  }
-  return x;
-}
 
 __device__ __forceinline__ uint32_t to_orig(const BfsParams& p, uint32_t u) {
   return p.orig_id ? p.orig_id[u] : u;
@@ -118,47 +68,111 @@ __device__ __forceinline__ uint32_t push_set(const BfsParams& p, uint32_t* qn, u
   return pos;
 }
 
-// Stage 1 of the lazy scheme: mark the next-visited bits of all pulled rows.
-template <typename MT, int SLOTS>
-__device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* qc, uint32_t len) {
-  constexpr int SIG = 8 * sizeof(MT);
+// Per-lane registers of G VSSs: SLOTS masks and row IDs each, plus alpha.
+template <typename MT, int SLOTS, int G>
+struct VssGroup {
+  MT m[G][SLOTS];
+  uint32_t u[G][SLOTS];
+  uint32_t alpha[G];
+};
+
+
+// Issues the mask and row-ID loads of the VSSs whose metadata sits in lanes
+// k0 .. k0 + G - 1 of (mb, me, ma); lanes >= cnt are empty.
+template <typename MT, int SLOTS, int G>
+__device__ __forceinline__ void load_group(const BfsParams& p, uint32_t mb, uint32_t me, uint32_t ma, uint32_t k0,
+                                           uint32_t cnt, VssGroup<MT, SLOTS, G>& g) {
   const MT* masks = static_cast<const MT*>(p.masks);
   const uint32_t lane = lane_id();
-  const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const uint32_t nw = (gridDim.x * blockDim.x) / kWave;
-  for (uint32_t q = wid; q < len; q += nw) {
-    const uint32_t v = qc[q];
-    const uint32_t beg = p.vss_beg[v], end = p.vss_beg[v + 1];
-    const uint32_t alpha = frontier_chunk<SIG>(p.front, p.v2r[v]);
-    MT m[SLOTS];
-    uint32_t u[SLOTS];
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const uint32_t src = k0 + k < cnt ? k0 + k : 63u;  // lane 63 holds an empty VSS when cnt < 64
+    const uint32_t beg = readlane(mb, src), end = k0 + k < cnt ? readlane(me, src) : beg;
+    g.alpha[k] = readlane(ma, src);
 #pragma unroll
     for (int r = 0; r < SLOTS; ++r) {
-      const uint32_t k = beg + lane + r * kWave;
-      const bool ok = k < end;
-      m[r] = ok ? masks[k] : MT(0);
-      u[r] = ok ? p.row_ids[k] : 0u;
-    }
-#pragma unroll
-    for (int r = 0; r < SLOTS; ++r) {
-      if ((uint32_t)m[r] & alpha) {
-        const uint32_t w = u[r] >> 5, bit = 1u << (u[r] & 31);
-        const uint2 cv = reinterpret_cast<const uint2*>(p.vis)[w];  // (current, next)
-        if (!((cv.x | cv.y) & bit)) atomicOr(p.vis + 2 * w + 1, bit);
-      }
+      const uint32_t idx = beg + lane + r * kWave;
+      const bool ok = idx < end;
+      g.m[k][r] = ok ? masks[idx] : MT(0);
+      g.u[k][r] = ok ? p.row_ids[idx] : 0u;
     }
   }
 }
 
-// Stage 2 of the lazy scheme: coalesced sweep over 32-vertex words.
-template <int SIG>
-__device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, uint32_t* qlen, int32_t level) {
-  constexpr int SPW = 32 / SIG;  // slice sets per word
+// Stage 1 driver shared by both schemes.  Wavefront w processes the queue
+// positions w, w + nw, w + 2 nw, ... (round-robin over all wavefronts of the
+// grid, Section 2.1.1).  Lane l first fetches the metadata of the wavefront's
+// l-th next position - VSS slice range and the sigma-bit frontier chunk alpha of
+// its slice set - so the dependent queue -> metadata -> frontier loads are paid
+// once per 64 VSSs; the values are then broadcast with readlane.  VSSs are taken
+// G at a time, and the next group's slice loads are issued before the current
+// group is applied.
+template <typename MT, int SLOTS, int G, class Apply>
+__device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, uint32_t len, const uint32_t* fcur,
+                                       Apply&& apply) {
+  constexpr int SIG = 8 * sizeof(MT);
   const uint32_t lane = lane_id();
   const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const uint32_t nw = (gridDim.x * blockDim.x) / kWave;
-  for (uint32_t base = wid * kWave; base < p.n_words; base += nw * kWave) {
-    const uint32_t t = base + lane;
+  for (uint32_t base = wid; base < len; base += nw * kWave) {
+    const uint32_t pos = base + lane * nw;
+    uint32_t mb = 0, me = 0, ma = 0;
+    if (pos < len) {
+      const uint32_t v = qc[pos];
+      mb = p.vss_beg[v];
+      me = p.vss_beg[v + 1];
+      ma = frontier_chunk<SIG>(fcur, p.v2r[v]);
+    }
+    const uint32_t cnt = min((uint32_t)kWave, (len - base + nw - 1) / nw);
+    VssGroup<MT, SLOTS, G> cur, nxt;
+    load_group<MT, SLOTS, G>(p, mb, me, ma, 0, cnt, cur);
+    for (uint32_t k = 0; k < cnt; k += G) {
+      if (k + G < cnt) load_group<MT, SLOTS, G>(p, mb, me, ma, k + G, cnt, nxt);
+      apply(cur);
+      cur = nxt;
+    }
+  }
+}
+
+// Stage 1 of the lazy scheme: set the next-visited bit of every pulled row.  The
+// visited words of all hits of a group are loaded back to back; the non-returning
+// atomic OR is issued only where the bit is not yet visible.
+template <typename MT, int SLOTS, int G>
+__device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* qc, uint32_t len) {
+  const uint2* vis2 = reinterpret_cast<const uint2*>(p.vis);
+  stage1<MT, SLOTS, G>(p, qc, len, p.front, [&](const VssGroup<MT, SLOTS, G>& g) {
+    uint2 cv[G][SLOTS];
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+      for (int r = 0; r < SLOTS; ++r) {
+        const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
+        cv[k][r] = vis2[hit ? (g.u[k][r] >> 5) : 0u];
+      }
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+      for (int r = 0; r < SLOTS; ++r) {
+        const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
+        const uint32_t bit = 1u << (g.u[k][r] & 31);
+        if (hit && !((cv[k][r].x | cv[k][r].y) & bit)) atomicOr(p.vis + 2 * (g.u[k][r] >> 5) + 1, bit);
+      }
+  });
+}
+
+// Stage 2 of the lazy scheme: coalesced sweep over 32-vertex words, one word per
+// thread.  Queue space is reserved once per workgroup (wavefront scans, then one
+// atomic add by thread 0): a reservation per wavefront would put thousands of
+// atomics on one counter per level.
+template <int SIG>
+__device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, uint32_t* qlen, int32_t level) {
+  constexpr int SPW = 32 / SIG;  // slice sets per word
+  __shared__ uint32_t s_wave[kMaxWaves];
+  __shared__ uint32_t s_base;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < p.n_words; b0 += gridDim.x * blockDim.x) {
+    const uint32_t t = b0 + threadIdx.x;
     uint32_t cnt = 0, pushmask = 0;
     if (t < p.n_words) {
       const uint2 cv = reinterpret_cast<const uint2*>(p.vis)[t];
@@ -182,68 +196,79 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, ui
         }
       }
     }
-    uint32_t total;
-    uint32_t pos = wave_reserve(qlen, cnt, total);
-    if (total != 0 && cnt != 0) {
+    const uint32_t incl = wave_inclusive_scan(cnt);
+    if (lane == kWave - 1) s_wave[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t run = 0;
+      for (uint32_t w = 0; w < nwaves; ++w) {
+        const uint32_t x = s_wave[w];
+        s_wave[w] = run;
+        run += x;
+      }
+      s_base = run ? atomicAdd(qlen, run) : 0u;
+    }
+    __syncthreads();
+    uint32_t pos = s_base + s_wave[wave] + incl - cnt;
+    if (cnt != 0) {
 #pragma unroll
       for (int i = 0; i < SPW; ++i)
         if (pushmask & (1u << i)) pos = push_set(p, qn, pos, t * SPW + i);
     }
+    __syncthreads();
   }
 }
 
-// Stage 1 of the eager scheme: claim, write the level, push the set's VSSs.
-template <typename MT, int SLOTS>
+// Stage 1 of the eager scheme: a hit whose vertex is not yet visited claims it with
+// a returning atomic OR on the next frontier; the claimer marks it visited, writes
+// its level, and - if it is the first claimer in its slice set's chunk - pushes the
+// set's VSS range (one queue reservation per wavefront and group).
+template <typename MT, int SLOTS, int G>
 __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t* qc, uint32_t len,
                                              const uint32_t* fc, uint32_t* fn, uint32_t* qn, uint32_t* qlen,
                                              int32_t level) {
   constexpr int SIG = 8 * sizeof(MT);
-  const MT* masks = static_cast<const MT*>(p.masks);
-  const uint32_t lane = lane_id();
-  const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const uint32_t nw = (gridDim.x * blockDim.x) / kWave;
-  for (uint32_t q = wid; q < len; q += nw) {
-    const uint32_t v = qc[q];
-    const uint32_t beg = p.vss_beg[v], end = p.vss_beg[v + 1];
-    const uint32_t alpha = frontier_chunk<SIG>(fc, p.v2r[v]);
-    MT m[SLOTS];
-    uint32_t u[SLOTS];
+  stage1<MT, SLOTS, G>(p, qc, len, fc, [&](const VssGroup<MT, SLOTS, G>& g) {
+    uint32_t vw[G][SLOTS];
 #pragma unroll
-    for (int r = 0; r < SLOTS; ++r) {
-      const uint32_t k = beg + lane + r * kWave;
-      const bool ok = k < end;
-      m[r] = ok ? masks[k] : MT(0);
-      u[r] = ok ? p.row_ids[k] : 0u;
-    }
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+      for (int r = 0; r < SLOTS; ++r) {
+        const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
+        vw[k][r] = p.vis[hit ? (g.u[k][r] >> 5) : 0u];
+      }
     uint32_t pushmask = 0, cnt = 0;
 #pragma unroll
-    for (int r = 0; r < SLOTS; ++r) {
-      if ((uint32_t)m[r] & alpha) {
-        const uint32_t x = u[r];
-        const uint32_t w = x >> 5, bit = 1u << (x & 31);
-        if (!(p.vis[w] & bit)) {
-          const uint32_t old = atomicOr(fn + w, bit);
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+      for (int r = 0; r < SLOTS; ++r) {
+        const uint32_t x = g.u[k][r];
+        const uint32_t bit = 1u << (x & 31);
+        const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
+        if (hit && !(vw[k][r] & bit)) {
+          const uint32_t old = atomicOr(fn + (x >> 5), bit);
           if (!(old & bit)) {
-            atomicOr(p.vis + w, bit);
+            atomicOr(p.vis + (x >> 5), bit);
             p.levels[to_orig(p, x)] = level;
             const uint32_t sh = (x & 31) & ~(uint32_t)(SIG - 1);
             if (((old >> sh) & chunk_mask<SIG>()) == 0) {
               const uint32_t ss = x / SIG;
-              pushmask |= 1u << r;
+              pushmask |= 1u << (k * SLOTS + r);
               cnt += p.real_ptrs[ss + 1] - p.real_ptrs[ss];
             }
           }
         }
       }
-    }
     uint32_t total;
     uint32_t pos = wave_reserve(qlen, cnt, total);
     if (total != 0 && cnt != 0) {
 #pragma unroll
-      for (int r = 0; r < SLOTS; ++r)
-        if (pushmask & (1u << r)) pos = push_set(p, qn, pos, u[r] / SIG);
+      for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int r = 0; r < SLOTS; ++r)
+          if (pushmask & (1u << (k * SLOTS + r))) pos = push_set(p, qn, pos, g.u[k][r] / SIG);
     }
-  }
+  });
 }
 
 // Clears the frontier chunks of the sets named by queue qold (eager scheme).
@@ -259,7 +284,7 @@ __device__ __forceinline__ void clear_chunks(const BfsParams& p, uint32_t* f, co
   }
 }
 
-template <typename MT, int SLOTS, bool LAZY>
+template <typename MT, int SLOTS, bool LAZY, int G>
 __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
   constexpr int SIG = 8 * sizeof(MT);
   uint32_t* ctrl = p.ctrl;
@@ -305,7 +330,7 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
       const uint32_t len = ld_relaxed(qlen + ((level - 1) % 3) * kLine);
       uint32_t* qnext_len = qlen + (level % 3) * kLine;
       if (tid == 0) __hip_atomic_store(qlen + ((level + 1) % 3) * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      stage1_lazy<MT, SLOTS>(p, qc, len);
+      stage1_lazy<MT, SLOTS, G>(p, qc, len);
       grid_barrier(ctrl);
       stage2_lazy<SIG>(p, qn, qnext_len, level);
       grid_barrier(ctrl);
@@ -322,7 +347,7 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
       uint32_t* fn = p.front + (level % 3) * p.n_words;
       uint32_t* fold = p.front + ((level + 1) % 3) * p.n_words;
       clear_chunks<SIG>(p, fold, qold, old_len);
-      stage1_eager<MT, SLOTS>(p, qc, len, fc, fn, qn, qnext_len, level);
+      stage1_eager<MT, SLOTS, G>(p, qc, len, fc, fn, qn, qnext_len, level);
       grid_barrier(ctrl);
       if (ld_relaxed(qnext_len) == 0) break;
     }
@@ -361,35 +386,40 @@ __global__ void parents_scan(BfsParams p, const int32_t* __restrict__ levels, in
 }
 
 template <typename MT, int SLOTS, bool LAZY>
-const void* sym() {
-  return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY>);
+const void* sym_group(uint32_t group) {
+  switch (group) {
+    case 1: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 1>);
+    case 2: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 2>);
+    case 4: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 4>);
+    default: return nullptr;
+  }
 }
 
 template <typename MT>
-const void* sym_slots(uint32_t slots, bool lazy) {
+const void* sym_slots(uint32_t slots, bool lazy, uint32_t group) {
   switch (slots) {
-    case 1: return lazy ? sym<MT, 1, true>() : sym<MT, 1, false>();
-    case 2: return lazy ? sym<MT, 2, true>() : sym<MT, 2, false>();
-    case 4: return lazy ? sym<MT, 4, true>() : sym<MT, 4, false>();
-    case 8: return lazy ? sym<MT, 8, true>() : sym<MT, 8, false>();
+    case 1: return lazy ? sym_group<MT, 1, true>(group) : sym_group<MT, 1, false>(group);
+    case 2: return lazy ? sym_group<MT, 2, true>(group) : sym_group<MT, 2, false>(group);
+    case 4: return lazy ? sym_group<MT, 4, true>(group) : sym_group<MT, 4, false>(group);
+    case 8: return lazy ? sym_group<MT, 8, true>(group) : sym_group<MT, 8, false>(group);
     default: return nullptr;
   }
 }
 
 }  // namespace
 
-const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy) {
+const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy, uint32_t group) {
   switch (sigma) {
-    case 8: return sym_slots<uint8_t>(slots, lazy);
-    case 16: return sym_slots<uint16_t>(slots, lazy);
-    case 32: return sym_slots<uint32_t>(slots, lazy);
+    case 8: return sym_slots<uint8_t>(slots, lazy, group);
+    case 16: return sym_slots<uint16_t>(slots, lazy, group);
+    case 32: return sym_slots<uint32_t>(slots, lazy, group);
     default: return nullptr;
   }
 }
 
-hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, bool lazy, uint32_t grid,
+hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, uint32_t grid,
                       uint32_t block, hipStream_t stream) {
-  const void* k = bfs_kernel_symbol(sigma, slots, lazy);
+  const void* k = bfs_kernel_symbol(sigma, slots, lazy, group);
   if (!k) return hipErrorInvalidValue;
   BfsParams copy = p;
   void* args[] = {&copy};

@@ -36,11 +36,36 @@ struct BfsParams {
 
 // Persistent single-source BFS; lazy selects Algorithm 3, otherwise Algorithm 2.
 // grid must be co-resident (the call uses a cooperative launch).
-hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, bool lazy, uint32_t grid,
+// group = VSSs whose slice loads a wavefront keeps in flight together (1, 2, 4).
+hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, uint32_t grid,
                       uint32_t block, hipStream_t stream);
 
 // Returns the kernel symbol used by launch_bfs (for occupancy queries).
-const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy);
+const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy, uint32_t group);
+
+// k-source BFS (k <= 64): per-vertex 64-bit frontier and visited words, bit j for
+// source j.
+constexpr uint32_t kMaxSources = 64;
+struct MultiParams {
+  const uint32_t* row_ids;
+  const void* masks;
+  const uint32_t* vss_beg;
+  const uint32_t* v2r;
+  const uint32_t* real_ptrs;
+  const uint32_t* orig_id;        // nullptr = identity
+  unsigned long long* vis;        // 2 * n: (current, next) per vertex
+  unsigned long long* front;      // n
+  uint32_t* queue;                // 2 * qcap
+  uint32_t* ctrl;                 // kCtrlWords
+  int32_t* levels;                // k * n, original IDs, row j for source j
+  uint32_t n, num_sets, num_vss, qcap, k, n_init_sets;
+  uint32_t src[kMaxSources];       // new labels
+  uint32_t init_sets[kMaxSources]; // distinct slice sets holding a source
+};
+
+hipError_t launch_bfs_multi(const MultiParams& p, uint32_t sigma, uint32_t slots, uint32_t grid, uint32_t block,
+                            hipStream_t stream);
+const void* bfs_multi_kernel_symbol(uint32_t sigma, uint32_t slots);
 
 // Parents post-pass: parent[v] = smallest original ID among the in-neighbours of v
 // on level level[v] - 1.  Ordinary launches on `stream`.

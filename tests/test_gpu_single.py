@@ -121,7 +121,7 @@ def test_repeated_runs_identical():
 def test_launch_shapes():
     gr = inputs.rmat_workload(12, 16, seed=2, permute_seed=7)
     srcs = inputs.sources(gr, seed=5, k=2)
-    for block, per_cu in ((64, 1), (256, 1), (1024, 1), (512, 4)):
+    for block, per_cu in ((64, 1), (256, 1), (1024, 1), (256, 4), (512, 2)):
         for update in ("eager", "lazy"):
             g = blest.Graph(gr, update=update, reorder="none", block=block, blocks_per_cu=per_cu)
             check_sources(gr, g, srcs)
