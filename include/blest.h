@@ -130,12 +130,25 @@ blest_status blest_bfs_multi(blest_handle h, const uint32_t* sources, uint32_t k
 
 /* One launch running g independent single-source BFSs, BFS i on graph hs[i] from
  * sources[i] (a HOST array), writing DEVICE int32[n_i] at levels_out[i] (a HOST
- * array of g device pointers).  All handles must live on the same device.  Each
- * BFS is owned by one workgroup whose bitmaps live in LDS, so graphs must have
- * n <= 131072; larger ones return INVALID_ARGUMENT.  The launch is an ordinary
- * (non-cooperative) kernel, so it can be captured into a HIP graph. */
+ * array of g device pointers).  All handles must live on the same device and share
+ * sigma and slots.  Each BFS is owned by one workgroup whose bitmaps live in LDS,
+ * so graphs must have n <= 131072; larger ones return INVALID_ARGUMENT.  The item
+ * table is uploaded synchronously; the launch itself is asynchronous on `stream`
+ * and the table is released once a later call sees the launch finished.  This is
+ * blest_batch_create + blest_batch_run in one call. */
 blest_status blest_bfs_many(const blest_handle* hs, const uint32_t* sources, uint32_t g,
                             int32_t* const* levels_out, void* stream);
+
+/* A reusable many-graphs launch: the item table (arguments as for blest_bfs_many)
+ * is built and uploaded once; blest_batch_run enqueues the single ordinary
+ * (non-cooperative) launch and nothing else, so it can be captured into a HIP
+ * graph and replayed.  The handles and output buffers must outlive the batch.
+ * blest_batch_destroy must not be called while a run is in flight. */
+typedef struct blest_batch* blest_batch_handle;
+blest_status blest_batch_create(const blest_handle* hs, const uint32_t* sources, uint32_t g,
+                                int32_t* const* levels_out, blest_batch_handle* out);
+blest_status blest_batch_run(blest_batch_handle b, void* stream);
+void blest_batch_destroy(blest_batch_handle b);
 
 /* Changes the launch settings of a built handle without rebuilding it: update
  * scheme (BLEST_UPDATE_*), threads per workgroup, workgroups per compute unit and

@@ -24,7 +24,7 @@ UPDATE = {"auto": 0, "eager": 1, "lazy": 2}
 EXPORT = {"new_id": (0, np.uint32), "real_ptrs": (1, np.uint32), "virtual_to_real": (2, np.uint32),
           "vss_begin": (3, np.uint32), "row_ids": (4, np.uint32), "masks": (5, np.uint8)}
 EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_bfs_multi", "blest_bfs_many",
-                    "blest_configure", "blest_stats", "blest_footprint", "blest_export", "blest_model_bytes", "blest_destroy",
+                    "blest_batch_create", "blest_batch_run", "blest_batch_destroy", "blest_configure", "blest_stats", "blest_footprint", "blest_export", "blest_model_bytes", "blest_destroy",
                     "blest_status_string")
 
 
@@ -75,6 +75,12 @@ def lib():
     L.blest_bfs_multi.restype = ctypes.c_int
     L.blest_bfs_many.argtypes = [ctypes.POINTER(vp), p32, u32, ctypes.POINTER(vp), vp]
     L.blest_bfs_many.restype = ctypes.c_int
+    L.blest_batch_create.argtypes = [ctypes.POINTER(vp), p32, u32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    L.blest_batch_create.restype = ctypes.c_int
+    L.blest_batch_run.argtypes = [vp, vp]
+    L.blest_batch_run.restype = ctypes.c_int
+    L.blest_batch_destroy.argtypes = [vp]
+    L.blest_batch_destroy.restype = None
     L.blest_configure.argtypes = [vp, i32, u32, u32, u32]
     L.blest_configure.restype = ctypes.c_int
     L.blest_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -254,3 +260,41 @@ def bfs_many(graphs, sources, outs=None, stream=None):
     ptrs = (ctypes.c_void_p * g)(*[o.data_ptr() for o in outs])
     _check("blest_bfs_many", lib().blest_bfs_many(hs, _p32(src), g, ptrs, _stream_ptr(stream)))
     return outs
+
+
+class Batch:
+    """A reusable many-graphs launch (blest_batch_*): BFS i on graphs[i] from
+    sources[i] into outs[i].  run() enqueues one ordinary launch, so it can be
+    captured into a CUDA/HIP graph.  Graphs and outputs must outlive the batch."""
+
+    def __init__(self, graphs, sources, outs=None):
+        import torch
+        g = len(graphs)
+        src = np.ascontiguousarray(sources, dtype=np.uint32)
+        if src.size != g:
+            raise ValueError("one source per graph")
+        if outs is None:
+            outs = [torch.empty(gr.n, dtype=torch.int32, device=torch.device("cuda", gr.device)) for gr in graphs]
+        for gr, o in zip(graphs, outs):
+            _require_int32_cuda(o, gr.n, "levels")
+        self.graphs, self.outs = list(graphs), list(outs)
+        hs = (ctypes.c_void_p * g)(*[gr.handle.value for gr in graphs])
+        ptrs = (ctypes.c_void_p * g)(*[o.data_ptr() for o in outs])
+        h = ctypes.c_void_p()
+        _check("blest_batch_create", lib().blest_batch_create(hs, _p32(src), g, ptrs, ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check("blest_batch_run", lib().blest_batch_run(self._h, _stream_ptr(stream)))
+        return self.outs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().blest_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

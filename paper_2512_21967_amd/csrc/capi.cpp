@@ -63,6 +63,8 @@ DeviceSerial g_serial[64];
 
 }  // namespace
 
+struct blest_batch;
+
 struct blest_graph {
   blest_options opt{};
   uint32_t n = 0;
@@ -88,7 +90,23 @@ struct blest_graph {
   uint32_t n_words() const { return (n + 31) / 32; }
 };
 
+// A device-resident table of (graph, source, output) items for the many-graphs
+// launch.  Items are sorted by stored slices, largest first.
+struct blest_batch {
+  int device = -1;
+  uint32_t g = 0, max_n = 0, sigma = 8, slots = 4;
+  DevBuf d_items, d_queues;
+};
+
 namespace {
+
+// Completed-launch bookkeeping for blest_bfs_many's internal batches.
+struct PendingBatch {
+  blest_batch* b;
+  hipEvent_t done;
+};
+std::mutex g_pending_mu;
+std::vector<PendingBatch> g_pending;
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -417,15 +435,115 @@ blest_status blest_bfs_multi(blest_handle h, const uint32_t* sources, uint32_t k
   }
 }
 
-blest_status blest_bfs_many(const blest_handle* hs, const uint32_t* sources, uint32_t g,
-                            int32_t* const* levels_out, void* stream) {
+blest_status blest_batch_create(const blest_handle* hs, const uint32_t* sources, uint32_t g,
+                                int32_t* const* levels_out, blest_batch_handle* out) {
+  if (!out) return BLEST_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
   if (!hs || !sources || !levels_out || g == 0) return BLEST_ERR_INVALID_ARGUMENT;
   for (uint32_t i = 0; i < g; ++i) {
     if (!hs[i] || !levels_out[i] || sources[i] >= hs[i]->n) return BLEST_ERR_INVALID_ARGUMENT;
-    if (!hs[i]->on_device) return BLEST_ERR_NO_DEVICE;
+    if (hs[i]->n > kManyMaxN) return BLEST_ERR_INVALID_ARGUMENT;
+    if (hs[i]->bvss.sigma != hs[0]->bvss.sigma || hs[i]->bvss.slots != hs[0]->bvss.slots)
+      return BLEST_ERR_INVALID_ARGUMENT;
   }
-  (void)stream;
-  return BLEST_ERR_INTERNAL;
+  for (uint32_t i = 0; i < g; ++i) {
+    if (!hs[i]->on_device) return BLEST_ERR_NO_DEVICE;
+    if (hs[i]->device != hs[0]->device) return BLEST_ERR_INVALID_ARGUMENT;
+  }
+  try {
+    if (hipSetDevice(hs[0]->device) != hipSuccess) return BLEST_ERR_DEVICE;
+    std::unique_ptr<blest_batch> b(new blest_batch);
+    b->device = hs[0]->device;
+    b->g = g;
+    b->sigma = hs[0]->bvss.sigma;
+    b->slots = hs[0]->bvss.slots;
+    std::vector<uint32_t> order(g);
+    for (uint32_t i = 0; i < g; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) {
+      return hs[a]->bvss.num_slices > hs[c]->bvss.num_slices;
+    });
+    uint64_t qwords = 0;
+    for (uint32_t i = 0; i < g; ++i) {
+      qwords += 2ull * std::max<uint32_t>(hs[i]->bvss.num_vss, 1);
+      b->max_n = std::max(b->max_n, hs[i]->n);
+    }
+    hipError_t e = b->d_queues.alloc(4 * qwords);
+    if (e == hipSuccess) e = b->d_items.alloc(sizeof(ManyItem) * g);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? BLEST_ERR_OUT_OF_MEMORY : BLEST_ERR_DEVICE;
+    std::vector<ManyItem> items(g);
+    uint64_t qoff = 0;
+    for (uint32_t r = 0; r < g; ++r) {
+      const blest_graph* h = hs[order[r]];
+      ManyItem& it = items[r];
+      it.row_ids = h->d_row_ids.as<uint32_t>();
+      it.masks = h->d_masks.p;
+      it.vss_beg = h->d_vss_beg.as<uint32_t>();
+      it.v2r = h->d_v2r.as<uint32_t>();
+      it.real_ptrs = h->d_real_ptrs.as<uint32_t>();
+      it.orig_id = h->identity ? nullptr : h->d_orig_id.as<uint32_t>();
+      it.levels = levels_out[order[r]];
+      it.queue = b->d_queues.as<uint32_t>() + qoff;
+      it.n = h->n;
+      it.num_vss = h->bvss.num_vss;
+      it.src = h->new_id[sources[order[r]]];
+      it.pad = 0;
+      qoff += 2ull * std::max<uint32_t>(h->bvss.num_vss, 1);
+    }
+    e = hipMemcpy(b->d_items.p, items.data(), sizeof(ManyItem) * g, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return BLEST_ERR_DEVICE;
+    *out = b.release();
+    return BLEST_OK;
+  } catch (const std::bad_alloc&) {
+    return BLEST_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    return BLEST_ERR_INTERNAL;
+  }
+}
+
+blest_status blest_batch_run(blest_batch_handle b, void* stream) {
+  if (!b) return BLEST_ERR_INVALID_ARGUMENT;
+  if (hipSetDevice(b->device) != hipSuccess) return BLEST_ERR_DEVICE;
+  hipError_t e = launch_bfs_many(b->d_items.as<ManyItem>(), b->g, b->max_n, b->sigma, b->slots,
+                                 static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BLEST_OK : BLEST_ERR_DEVICE;
+}
+
+void blest_batch_destroy(blest_batch_handle b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  delete b;
+}
+
+blest_status blest_bfs_many(const blest_handle* hs, const uint32_t* sources, uint32_t g,
+                            int32_t* const* levels_out, void* stream) {
+  blest_batch* b = nullptr;
+  blest_status st = blest_batch_create(hs, sources, g, levels_out, &b);
+  if (st != BLEST_OK) return st;
+  st = blest_batch_run(b, stream);
+  hipEvent_t done = nullptr;
+  if (st == BLEST_OK && (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess ||
+                         hipEventRecord(done, static_cast<hipStream_t>(stream)) != hipSuccess))
+    st = BLEST_ERR_DEVICE;
+  std::lock_guard<std::mutex> lk(g_pending_mu);
+  // free the tables of earlier calls whose launches have finished
+  for (size_t i = 0; i < g_pending.size();) {
+    if (hipEventQuery(g_pending[i].done) == hipSuccess) {
+      (void)hipEventDestroy(g_pending[i].done);
+      blest_batch_destroy(g_pending[i].b);
+      g_pending[i] = g_pending.back();
+      g_pending.pop_back();
+    } else {
+      ++i;
+    }
+  }
+  if (st == BLEST_OK) {
+    g_pending.push_back({b, done});
+  } else {
+    if (done) (void)hipEventDestroy(done);
+    (void)hipDeviceSynchronize();
+    blest_batch_destroy(b);
+  }
+  return st;
 }
 
 blest_status blest_configure(blest_handle h, int32_t update, uint32_t block, uint32_t blocks_per_cu, uint32_t group) {

@@ -67,6 +67,26 @@ hipError_t launch_bfs_multi(const MultiParams& p, uint32_t sigma, uint32_t slots
                             hipStream_t stream);
 const void* bfs_multi_kernel_symbol(uint32_t sigma, uint32_t slots);
 
+// Many independent single-source BFSs in one ordinary launch: workgroup i runs
+// item i start to finish, with its bitmaps in LDS and only workgroup barriers.
+struct ManyItem {
+  const uint32_t* row_ids;
+  const void* masks;
+  const uint32_t* vss_beg;
+  const uint32_t* v2r;
+  const uint32_t* real_ptrs;
+  const uint32_t* orig_id;  // nullptr = identity
+  int32_t* levels;          // n, original IDs
+  uint32_t* queue;          // 2 * max(num_vss, 1)
+  uint32_t n, num_vss, src, pad;
+};
+constexpr uint32_t kManyMaxN = 131072;  // LDS holds 3 bits per vertex
+constexpr uint32_t kManyBlock = 512;
+
+// items: device array of g descriptors; all items share sigma and slots.
+hipError_t launch_bfs_many(const ManyItem* items, uint32_t g, uint32_t max_n, uint32_t sigma, uint32_t slots,
+                           hipStream_t stream);
+
 // Parents post-pass: parent[v] = smallest original ID among the in-neighbours of v
 // on level level[v] - 1.  Ordinary launches on `stream`.
 hipError_t launch_parents(const BfsParams& p, uint32_t sigma, const int32_t* levels, int32_t* parents,
