@@ -77,6 +77,9 @@ typedef struct {
   uint32_t block;      /* threads per workgroup of the persistent kernels, a multiple of 64 (0 = 1024) */
   uint32_t blocks_per_cu; /* persistent workgroups per compute unit (0 = 1); block * blocks_per_cu <= 1024 */
   uint32_t group;      /* VSSs whose slice loads a wavefront keeps in flight: 1, 2 or 4 (0 = 2) */
+  uint32_t ranges;     /* row ranges of the LDS-resident visited bits of the lazy kernel: a power of
+                          two <= 32; every VSS also stays inside one range (0 = auto: split only
+                          for the lazy scheme, into the fewest ranges whose bitmap fits 64 KB) */
 } blest_options;
 
 typedef struct {
@@ -92,6 +95,8 @@ typedef struct {
   int32_t social_like;          /* Section 2.2.1 test */
   int32_t reorder_used;         /* BLEST_REORDER_* actually applied */
   int32_t update_used;          /* BLEST_UPDATE_* actually used */
+  uint32_t nranges;             /* row ranges of the VSS partition */
+  uint32_t range_len;           /* rows per range */
   uint64_t bvss_device_bytes;   /* static arrays resident on the device */
   uint64_t bvss_bytes_table3;   /* the paper's accounting (Table 3) for this structure */
   double reorder_seconds;       /* host ordering time */
@@ -175,7 +180,8 @@ enum {
   BLEST_EXPORT_VIRTUAL_TO_REAL = 2, /* uint32[num_vss] */
   BLEST_EXPORT_VSS_BEGIN = 3,       /* uint32[num_vss + 1]: first slice of each VSS */
   BLEST_EXPORT_ROW_IDS = 4,         /* uint32[num_slices], new labels */
-  BLEST_EXPORT_MASKS = 5            /* sigma/8 bytes per slice, little-endian, bit j = column j */
+  BLEST_EXPORT_MASKS = 5,           /* sigma/8 bytes per slice, little-endian, bit j = column j */
+  BLEST_EXPORT_VSS_RANGE = 6        /* uint8[num_vss]: row range of each VSS */
 };
 blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t capacity_bytes,
                           uint64_t* size_bytes);

@@ -43,7 +43,7 @@ struct DevBuf {
 // Per-stream scratch of the single-source kernels.  Calls on one stream are
 // ordered, so reusing the stream's workspace is safe without host waits.
 struct SingleWorkspace {
-  DevBuf vis, front, queue, ctrl;
+  DevBuf vis, mark, front, queue, ctrl;
 };
 
 // Per-stream scratch of the k-source kernel: 64-bit visited pairs and frontier
@@ -81,7 +81,8 @@ struct blest_graph {
   // device state
   bool on_device = false;
   int device = -1;
-  DevBuf d_row_ids, d_masks, d_vss_beg, d_v2r, d_real_ptrs, d_orig_id;
+  DevBuf d_row_ids, d_masks, d_vss_beg, d_v2r, d_real_ptrs, d_orig_id, d_vss_range;
+  uint32_t nranges = 1, range_len = 0, range_words = 0;
   uint32_t grid = 0, block = 0;
   std::mutex ws_mu;
   std::map<void*, std::unique_ptr<SingleWorkspace>> single_ws;
@@ -134,6 +135,7 @@ bool valid_options(const blest_options& o) {
   // that filled all of them (1024 x 2) hung once, cause not identified.
   if ((uint64_t)o.block * (o.blocks_per_cu ? o.blocks_per_cu : 1) > 1024) return false;
   if (o.group != 1 && o.group != 2 && o.group != 4) return false;
+  if (o.ranges > kMaxRanges || (o.ranges & (o.ranges - 1)) != 0) return false;
   return true;
 }
 
@@ -157,6 +159,7 @@ blest_status to_device(blest_graph* g) {
   if (e == hipSuccess) e = upload(g->d_v2r, b.v2r);
   if (e == hipSuccess) e = upload(g->d_real_ptrs, b.real_ptrs);
   if (e == hipSuccess && !g->identity) e = upload(g->d_orig_id, g->orig_id);
+  if (e == hipSuccess) e = upload(g->d_vss_range, b.vss_range);
   if (e == hipErrorOutOfMemory) return BLEST_ERR_OUT_OF_MEMORY;
   if (e != hipSuccess) return BLEST_ERR_DEVICE;
   blest_status st = set_grid(g);
@@ -175,13 +178,17 @@ blest_status set_grid(blest_graph* g) {
   uint32_t per_cu = UINT32_MAX;
   for (int lazy = 0; lazy < 2; ++lazy) {
     int nb = 0;
-    const void* k = bfs_kernel_symbol(b.sigma, b.slots, lazy != 0, g->opt.group);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)g->block, 0) != hipSuccess || nb <= 0)
+    const bool lds = lazy && g->range_words > 0;
+    const void* k = bfs_kernel_symbol(b.sigma, b.slots, lazy != 0, g->opt.group, lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)g->block, lds ? 4 * g->range_words : 0) !=
+            hipSuccess ||
+        nb <= 0)
       return BLEST_ERR_DEVICE;
     per_cu = std::min<uint32_t>(per_cu, (uint32_t)nb);
   }
   per_cu = std::min<uint32_t>(per_cu, g->opt.blocks_per_cu);
-  g->grid = per_cu * (uint32_t)cus;
+  g->grid = per_cu * (uint32_t)cus / g->nranges * g->nranges;
+  if (g->grid == 0) return BLEST_ERR_DEVICE;
   int nbm = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbm, bfs_multi_kernel_symbol(b.sigma, b.slots), (int)g->block, 0) !=
           hipSuccess ||
@@ -197,7 +204,8 @@ SingleWorkspace* single_workspace(blest_graph* g, void* stream, blest_status* st
   if (it != g->single_ws.end()) return it->second.get();
   auto ws = std::make_unique<SingleWorkspace>();
   const size_t nw = g->n_words();
-  hipError_t e = ws->vis.alloc(sizeof(uint32_t) * 2 * nw);
+  hipError_t e = ws->vis.alloc(sizeof(uint32_t) * nw);
+  if (e == hipSuccess) e = ws->mark.alloc(32 * nw);
   if (e == hipSuccess) e = ws->front.alloc(sizeof(uint32_t) * 3 * nw);
   if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 3 * std::max<size_t>(g->bvss.num_vss, 1));
   if (e == hipSuccess) e = ws->ctrl.alloc(sizeof(uint32_t) * kCtrlWords);
@@ -265,6 +273,10 @@ BfsParams base_params(const blest_graph* g) {
   p.num_sets = g->bvss.num_sets;
   p.num_vss = g->bvss.num_vss;
   p.qcap = std::max<uint32_t>(g->bvss.num_vss, 1);
+  p.vss_range = g->d_vss_range.as<uint8_t>();
+  p.nranges = g->nranges;
+  p.range_len = g->range_len;
+  p.range_words = g->range_words;
   return p;
 }
 
@@ -284,6 +296,7 @@ void blest_default_options(blest_options* o) {
   o->block = 1024;
   o->blocks_per_cu = 1;
   o->group = 2;
+  o->ranges = 0;
 }
 
 blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, const uint32_t* col_idx,
@@ -338,16 +351,33 @@ blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, cons
     }
     double t1 = now_s();
     g->reorder_seconds = t1 - t0;
-    rc = build_bvss(work, o.sigma, o.slots, T, g->bvss);
+    rc = build_slices(work, o.sigma, o.slots, T, g->bvss);
     if (rc != kOk) return map_rc(rc);
-    g->build_seconds = now_s() - t1;
     g->compression = g->bvss.num_slices ? (double)g->m / ((double)g->bvss.num_slices * o.sigma) : 0.0;
     g->u_div_paper = update_divergence(g->bvss, 32, 32 / o.sigma);
-    g->u_div_native = update_divergence(g->bvss, 64, o.slots);
     if (o.update == BLEST_UPDATE_AUTO)
       g->lazy = g->social && g->u_div_paper > 25000.0;
     else
       g->lazy = o.update == BLEST_UPDATE_LAZY;
+    // Row ranges: the lazy kernel keeps one range's visited bits per workgroup in
+    // LDS.  Auto picks the fewest ranges (a power of two) whose bitmap fits, and
+    // splits only when the lazy scheme is in use.
+    const uint32_t nw = (n + 31) / 32;
+    uint32_t R = o.ranges;
+    if (R == 0) {
+      R = 1;
+      if (g->lazy)
+        while (R < kMaxRanges && (uint64_t)((nw + R - 1) / R) * 4 > kMaxLdsRangeBytes) R *= 2;
+    }
+    const uint32_t rw = (nw + R - 1) / R;  // visited words per range
+    g->nranges = R;
+    g->range_len = rw * 32;
+    g->range_words = (uint64_t)rw * 4 <= kMaxLdsRangeBytes ? rw : 0;
+    rc = partition_vss(g->bvss, R > 1 ? g->range_len : 0, T);
+    if (rc != kOk) return map_rc(rc);
+    if (g->bvss.num_vss >= (1u << (32 - kRangeBits))) return BLEST_ERR_TOO_LARGE;
+    g->build_seconds = now_s() - t1;
+    g->u_div_native = update_divergence(g->bvss, 64, 0);
     if (o.device >= 0) {
       g->device = o.device;
       blest_status st = to_device(g.get());
@@ -374,6 +404,7 @@ blest_status blest_bfs(blest_handle h, uint32_t source, int32_t* levels_out, int
     if (!ws) return st;
     BfsParams p = base_params(h);
     p.vis = ws->vis.as<uint32_t>();
+    p.mark = ws->mark.as<uint8_t>();
     p.front = ws->front.as<uint32_t>();
     p.queue = ws->queue.as<uint32_t>();
     p.ctrl = ws->ctrl.as<uint32_t>();
@@ -592,7 +623,9 @@ blest_status blest_stats(blest_handle h, blest_stats_t* o) {
   o->social_like = h->social;
   o->reorder_used = h->reorder_used;
   o->update_used = h->lazy ? BLEST_UPDATE_LAZY : BLEST_UPDATE_EAGER;
-  o->bvss_device_bytes = b.num_slices * (4 + b.sigma / 8) + 4ull * (2ull * b.num_vss + 1) +
+  o->nranges = h->nranges;
+  o->range_len = h->range_len;
+  o->bvss_device_bytes = b.num_slices * (4 + b.sigma / 8) + 4ull * (2ull * b.num_vss + 1) + b.num_vss +
                          4ull * (b.num_sets + 1) + (h->identity ? 0 : 4ull * h->n);
   o->bvss_bytes_table3 = b.num_slices * (4 + b.sigma / 8) + 4ull * (b.num_vss + b.num_sets);
   o->reorder_seconds = h->reorder_seconds;
@@ -612,7 +645,7 @@ blest_status blest_footprint(blest_handle h, uint32_t k, uint64_t* bytes) {
   const uint64_t q = 3ull * std::max<uint32_t>(h->bvss.num_vss, 1) * 4;
   uint64_t ws;
   if (k == 1)
-    ws = 5 * nw * 4 + q + kCtrlWords * 4;
+    ws = 4 * nw * 4 + 32 * nw + q + kCtrlWords * 4;
   else
     ws = 3ull * h->n * 8 + q + kCtrlWords * 4;  // 64-bit frontier/visited rows
   *bytes = ws + (uint64_t)k * h->n * 4;
@@ -631,6 +664,7 @@ blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t cap
     case BLEST_EXPORT_VSS_BEGIN: src = b.vss_beg.data(); bytes = 4ull * b.vss_beg.size(); break;
     case BLEST_EXPORT_ROW_IDS: src = b.row_ids.data(); bytes = 4ull * b.row_ids.size(); break;
     case BLEST_EXPORT_MASKS: src = b.masks.data(); bytes = b.masks.size(); break;
+    case BLEST_EXPORT_VSS_RANGE: src = b.vss_range.data(); bytes = b.vss_range.size(); break;
     default: return BLEST_ERR_INVALID_ARGUMENT;
   }
   *size = bytes;

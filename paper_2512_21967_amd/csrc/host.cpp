@@ -388,7 +388,7 @@ void rcm(const Csr& u, std::vector<uint32_t>& new_id) {
 // (sigma*i + j) -> u exists.  The slices of set i therefore come from merging the
 // out-lists of vertices sigma*i .. sigma*i + sigma - 1.
 // ---------------------------------------------------------------------------
-int build_bvss(const Csr& g, uint32_t sigma, uint32_t slots, int threads, Bvss& b) {
+int build_slices(const Csr& g, uint32_t sigma, uint32_t slots, int threads, Bvss& b) {
   b.n = g.n;
   b.sigma = sigma;
   b.slots = slots;
@@ -428,13 +428,8 @@ int build_bvss(const Csr& g, uint32_t sigma, uint32_t slots, int threads, Bvss& 
     }
   });
   b.set_beg.assign((size_t)S + 1, 0);
-  b.real_ptrs.assign((size_t)S + 1, 0);
-  for (uint32_t s = 0; s < S; ++s) {
-    b.set_beg[s + 1] = b.set_beg[s] + set_cnt[s];
-    b.real_ptrs[s + 1] = b.real_ptrs[s] + (set_cnt[s] + b.tau - 1) / b.tau;
-  }
+  for (uint32_t s = 0; s < S; ++s) b.set_beg[s + 1] = b.set_beg[s] + set_cnt[s];
   b.num_slices = b.set_beg[S];
-  b.num_vss = b.real_ptrs[S];
   b.row_ids.resize(b.num_slices);
   b.masks.resize(b.num_slices * mb);
   parallel_chunks(nchunks, 1, threads, [&](uint64_t c0, uint64_t c1) {
@@ -446,13 +441,46 @@ int build_bvss(const Csr& g, uint32_t sigma, uint32_t slots, int threads, Bvss& 
       std::vector<uint8_t>().swap(masks[c]);
     }
   });
+  return kOk;
+}
+
+int partition_vss(Bvss& b, uint32_t range_len, int threads) {
+  const uint32_t S = b.num_sets;
+  // VSS partition: cut each set's row-sorted slices into runs of at most tau that
+  // also stay inside one row range of range_len IDs (no range split if 0).
+  b.range_len = range_len;
+  auto range_of = [&](uint32_t row) { return range_len ? row / range_len : 0u; };
+  auto walk = [&](uint32_t s, auto&& emit) {
+    uint32_t k = b.set_beg[s], e = b.set_beg[s + 1];
+    while (k < e) {
+      const uint32_t r = range_of(b.row_ids[k]);
+      uint32_t j = k + 1;
+      while (j < e && j - k < b.tau && range_of(b.row_ids[j]) == r) ++j;
+      emit(k, r);
+      k = j;
+    }
+  };
+  std::vector<uint32_t> vss_cnt(S, 0);
+  parallel_chunks(S, 4096, threads, [&](uint64_t lo, uint64_t hi) {
+    for (uint64_t s = lo; s < hi; ++s) walk((uint32_t)s, [&](uint32_t, uint32_t) { ++vss_cnt[s]; });
+  });
+  b.real_ptrs.assign((size_t)S + 1, 0);
+  for (uint32_t s = 0; s < S; ++s) b.real_ptrs[s + 1] = b.real_ptrs[s] + vss_cnt[s];
+  b.num_vss = b.real_ptrs[S];
   b.v2r.resize(b.num_vss);
   b.vss_beg.resize((size_t)b.num_vss + 1);
-  for (uint32_t s = 0; s < S; ++s)
-    for (uint32_t v = b.real_ptrs[s]; v < b.real_ptrs[s + 1]; ++v) {
-      b.v2r[v] = s;
-      b.vss_beg[v] = b.set_beg[s] + (v - b.real_ptrs[s]) * b.tau;
+  b.vss_range.resize(b.num_vss);
+  parallel_chunks(S, 4096, threads, [&](uint64_t lo, uint64_t hi) {
+    for (uint64_t s = lo; s < hi; ++s) {
+      uint32_t v = b.real_ptrs[s];
+      walk((uint32_t)s, [&](uint32_t k, uint32_t r) {
+        b.v2r[v] = (uint32_t)s;
+        b.vss_beg[v] = k;
+        b.vss_range[v] = (uint8_t)r;
+        ++v;
+      });
     }
+  });
   b.vss_beg[b.num_vss] = (uint32_t)b.num_slices;
   return kOk;
 }
@@ -461,24 +489,28 @@ double update_divergence(const Bvss& b, uint32_t lanes, uint32_t slots_per_lane)
   const uint32_t tau = lanes * slots_per_lane;
   double sum = 0;
   uint64_t nvss = 0;
-  for (uint32_t s = 0; s < b.num_sets; ++s) {
-    uint32_t lo = b.set_beg[s], hi = b.set_beg[s + 1];
-    for (uint32_t v = lo; v < hi; v += tau) {
-      uint32_t ve = std::min(hi, v + tau);
-      double cols = 0;
-      uint32_t ncols = 0;
-      for (uint32_t c = v; c < ve; c += lanes) {
-        uint32_t ce = std::min(ve, c + lanes);
-        double mean = 0;
-        for (uint32_t k = c; k < ce; ++k) mean += b.row_ids[k];
-        mean /= (ce - c);
-        double var = 0;
-        for (uint32_t k = c; k < ce; ++k) var += (b.row_ids[k] - mean) * (b.row_ids[k] - mean);
-        cols += std::sqrt(var / (ce - c));
-        ++ncols;
-      }
-      sum += cols / ncols;
-      ++nvss;
+  auto vss = [&](uint32_t v, uint32_t ve) {
+    double cols = 0;
+    uint32_t ncols = 0;
+    for (uint32_t c = v; c < ve; c += lanes) {
+      uint32_t ce = std::min(ve, c + lanes);
+      double mean = 0;
+      for (uint32_t k = c; k < ce; ++k) mean += b.row_ids[k];
+      mean /= (ce - c);
+      double var = 0;
+      for (uint32_t k = c; k < ce; ++k) var += (b.row_ids[k] - mean) * (b.row_ids[k] - mean);
+      cols += std::sqrt(var / (ce - c));
+      ++ncols;
+    }
+    sum += cols / ncols;
+    ++nvss;
+  };
+  if (slots_per_lane == 0) {  // this layout's own VSSs, `lanes` per column
+    for (uint32_t v = 0; v < b.num_vss; ++v) vss(b.vss_beg[v], b.vss_beg[v + 1]);
+  } else {  // each set cut into VSSs of tau slices
+    for (uint32_t s = 0; s < b.num_sets; ++s) {
+      uint32_t lo = b.set_beg[s], hi = b.set_beg[s + 1];
+      for (uint32_t v = lo; v < hi; v += tau) vss(v, std::min(hi, v + tau));
     }
   }
   return nvss ? sum / nvss : 0.0;

@@ -42,18 +42,21 @@ void jaccard_windows(const Csr& g, const Csr& gt, uint32_t sigma, uint32_t w, in
 void rcm(const Csr& u, std::vector<uint32_t>& new_id);
 
 // The static BVSS arrays (Section 2.1) in this library's layout: the slices of a
-// slice set are sorted by row and cut into VSSs of at most tau = 64 * slots; VSS v
-// owns slices [vss_beg[v], vss_beg[v+1]) stored contiguously, so lane l of a
-// wavefront handles slices l, l + 64, ... of the VSS (column-major placement,
-// Section 2.1.2) and nothing is padded.
+// slice set are sorted by row and cut into VSSs of at most tau = 64 * slots, a cut
+// also falling at every multiple of range_len in row ID (when range_len > 0) so
+// that each VSS pulls rows of one row range only; VSS v owns slices
+// [vss_beg[v], vss_beg[v+1]) stored contiguously, so lane l of a wavefront handles
+// slices l, l + 64, ... of the VSS (column-major placement, Section 2.1.2) and
+// nothing is padded.
 struct Bvss {
-  uint32_t n = 0, sigma = 8, slots = 4, tau = 256;
+  uint32_t n = 0, sigma = 8, slots = 4, tau = 256, range_len = 0;
   uint32_t num_sets = 0, num_vss = 0;
   uint64_t num_slices = 0;
   std::vector<uint32_t> real_ptrs;  // num_sets + 1
   std::vector<uint32_t> v2r;        // num_vss
   std::vector<uint32_t> vss_beg;    // num_vss + 1
   std::vector<uint32_t> set_beg;    // num_sets + 1 (first slice of each set)
+  std::vector<uint8_t> vss_range;   // num_vss: row range of each VSS
   std::vector<uint32_t> row_ids;    // num_slices
   std::vector<uint8_t> masks;       // num_slices * sigma / 8
   uint32_t mask_bytes() const { return sigma / 8; }
@@ -64,10 +67,13 @@ struct Bvss {
   }
 };
 
-int build_bvss(const Csr& g, uint32_t sigma, uint32_t slots, int threads, Bvss& out);
+// Slices of every set (set_beg, row_ids, masks); then the VSS partition.
+int build_slices(const Csr& g, uint32_t sigma, uint32_t slots, int threads, Bvss& out);
+int partition_vss(Bvss& b, uint32_t range_len, int threads);
 
 // Update divergence (Section 2.2.1) when each set's sorted slices are cut into
-// VSSs of lanes * slots_per_lane and columns of `lanes` consecutive slices.
+// VSSs of lanes * slots_per_lane and columns of `lanes` consecutive slices;
+// slots_per_lane = 0 uses this layout's own VSSs.
 double update_divergence(const Bvss& b, uint32_t lanes, uint32_t slots_per_lane);
 
 }  // namespace blest

@@ -13,11 +13,14 @@
 //     Eq. (1) with a single frontier column, done with one VALU AND.  gfx950 has
 //     no 1-bit matrix instruction, and a single frontier vector is not a dense
 //     tile, so no MFMA is used here.
-//   * Lazy scheme (Algorithm 3, Section 3.2): a hit only sets the vertex's bit in
-//     the next-visited bitmap with a non-returning atomic OR (skipped when the bit
-//     is already visible); a coalesced sweep over 32-vertex words then writes the
-//     levels, the next frontier and the next queue, with one queue reservation
-//     per wavefront (ballot-free prefix scan + one atomic add).
+//   * Lazy scheme (Algorithm 3, Section 3.2): a hit on a row not visited when the
+//     level started only marks the row, with a plain one-byte store into its
+//     reached byte (the paper's non-returning atomic OR, made cheaper still: the
+//     marks are idempotent, so no read-modify-write is needed); a coalesced sweep
+//     over 32-vertex words then folds the reached bytes into the visited bits and
+//     writes the levels, the next frontier and the next queue, with one queue
+//     reservation per workgroup.  With row ranges, each workgroup checks hits
+//     against its range's visited bits held in LDS.
 //   * Eager scheme (Algorithm 2): a hit claims the vertex with a returning atomic
 //     OR on the next frontier; the first claimer in a slice set's chunk pushes the
 //     set's VSS range.  The visited bitmap (not the level array) filters hits.
@@ -32,6 +35,12 @@
 
 namespace blest {
 namespace {
+
+// Queue entry of VSS v: its ID and row range.
+struct RangeEntry {
+  const uint8_t* vss_range;
+  __device__ uint32_t operator()(uint32_t v) const { return (v << kRangeBits) | vss_range[v]; }
+};
 
 __device__ __forceinline__ uint32_t to_orig(const BfsParams& p, uint32_t u) {
   return p.orig_id ? p.orig_id[u] : u;
@@ -59,13 +68,6 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t* qlen, uint32_t cnt, u
   if (total != 0 && lane_id() == 0) base = atomicAdd(qlen, total);
   base = __shfl(base, 0, kWave);
   return base + incl - cnt;
-}
-
-// Appends the VSS range of slice set ss at qn[pos ...].
-__device__ __forceinline__ uint32_t push_set(const BfsParams& p, uint32_t* qn, uint32_t pos, uint32_t ss) {
-  const uint32_t b = p.real_ptrs[ss], e = p.real_ptrs[ss + 1];
-  for (uint32_t v = b; v < e; ++v) qn[pos++] = v;
-  return pos;
 }
 
 // Per-lane registers of G VSSs: SLOTS masks and row IDs each, plus alpha.
@@ -118,7 +120,7 @@ __device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, u
     const uint32_t pos = base + lane * nw;
     uint32_t mb = 0, me = 0, ma = 0;
     if (pos < len) {
-      const uint32_t v = qc[pos];
+      const uint32_t v = qc[pos] >> kRangeBits;
       mb = p.vss_beg[v];
       me = p.vss_beg[v + 1];
       ma = frontier_chunk<SIG>(fcur, p.v2r[v]);
@@ -134,34 +136,111 @@ __device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, u
   }
 }
 
-// Stage 1 of the lazy scheme: set the next-visited bit of every pulled row.  The
-// visited words of all hits of a group are loaded back to back; the non-returning
-// atomic OR is issued only where the bit is not yet visible.
+// Stage 1 of the lazy scheme: mark every pulled row that was not visited when the
+// level started.  The current-visited words of all hits of a group are loaded back
+// to back; a mark is a plain one-byte store of 1 into the row's reached byte.  The
+// stores are idempotent and all write the same value, so no read-modify-write is
+// needed (device-scope atomic ORs cost an order of magnitude more on MI355X).
 template <typename MT, int SLOTS, int G>
 __device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* qc, uint32_t len) {
-  const uint2* vis2 = reinterpret_cast<const uint2*>(p.vis);
   stage1<MT, SLOTS, G>(p, qc, len, p.front, [&](const VssGroup<MT, SLOTS, G>& g) {
-    uint2 cv[G][SLOTS];
+    uint32_t cw[G][SLOTS];
 #pragma unroll
     for (int k = 0; k < G; ++k)
 #pragma unroll
       for (int r = 0; r < SLOTS; ++r) {
         const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
-        cv[k][r] = vis2[hit ? (g.u[k][r] >> 5) : 0u];
+        cw[k][r] = p.vis[hit ? (g.u[k][r] >> 5) : 0u];
       }
 #pragma unroll
     for (int k = 0; k < G; ++k)
 #pragma unroll
       for (int r = 0; r < SLOTS; ++r) {
         const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
-        const uint32_t bit = 1u << (g.u[k][r] & 31);
-        if (hit && !((cv[k][r].x | cv[k][r].y) & bit)) atomicOr(p.vis + 2 * (g.u[k][r] >> 5) + 1, bit);
+        if (hit && !(cw[k][r] & (1u << (g.u[k][r] & 31)))) p.mark[g.u[k][r]] = 1;
       }
   });
 }
 
+// Stage 1 of the lazy scheme with the visited bits in LDS.  Rows are split into
+// nranges ranges; workgroup b serves range b % nranges (with 8 ranges, one per XCD
+// under round-robin dispatch) and holds that range's current visited words in LDS,
+// reloaded at the start of every level.  Each wavefront of the range group looks at
+// 64 queue positions at a time, strided by the group's wavefront count so that
+// short queues still spread over the group, keeps the entries of its range, stages their
+// metadata in lanes and processes them G at a time.  A hit's check and its
+// de-duplication are LDS operations; only the first mark of a vertex within a
+// workgroup reaches global memory (a one-byte store into its reached byte).
+template <typename MT, int SLOTS, int G>
+__device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32_t* qc, uint32_t len, uint32_t* lds) {
+  constexpr int SIG = 8 * sizeof(MT);
+  const uint32_t R = p.nranges;
+  const uint32_t r = blockIdx.x % R;
+  const uint32_t w0 = r * (p.range_len >> 5);
+  for (uint32_t i = threadIdx.x; i < p.range_words; i += blockDim.x)
+    lds[i] = (w0 + i < p.n_words) ? p.vis[w0 + i] : 0u;
+  __syncthreads();
+  const uint32_t lane = lane_id();
+  const uint32_t W = blockDim.x / kWave;
+  const uint32_t wg = (blockIdx.x / R) * W + threadIdx.x / kWave;
+  const uint32_t nwg = (gridDim.x / R) * W;
+  const uint32_t rbase = r * p.range_len;
+  for (uint32_t base = wg; base < len; base += nwg * kWave) {
+    const uint32_t pos = base + lane * nwg;
+    const uint32_t e = pos < len ? qc[pos] : 0u;
+    const bool mine = pos < len && (e & (kMaxRanges - 1)) == r;
+    uint64_t pick = __ballot(mine);
+    uint32_t mb = 0, me = 0, ma = 0;
+    if (mine) {
+      const uint32_t v = e >> kRangeBits;
+      mb = p.vss_beg[v];
+      me = p.vss_beg[v + 1];
+      ma = frontier_chunk<SIG>(p.front, p.v2r[v]);
+    }
+    while (pick) {
+      // the next G picked lanes (uniform); missing ones read an empty VSS
+      uint32_t src[G];
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        src[k] = pick ? (uint32_t)(__ffsll((unsigned long long)pick) - 1) : 64u;
+        pick &= pick - 1;
+      }
+      VssGroup<MT, SLOTS, G> g;
+      const MT* masks = static_cast<const MT*>(p.masks);
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const bool ok_k = src[k] < 64u;
+        const uint32_t beg = ok_k ? readlane(mb, src[k]) : 0u;
+        const uint32_t end = ok_k ? readlane(me, src[k]) : 0u;
+        g.alpha[k] = ok_k ? readlane(ma, src[k]) : 0u;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+          const uint32_t idx = beg + lane + q * kWave;
+          const bool ok = idx < end;
+          g.m[k][q] = ok ? masks[idx] : MT(0);
+          g.u[k][q] = ok ? p.row_ids[idx] : 0u;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+          if ((uint32_t)g.m[k][q] & g.alpha[k]) {
+            const uint32_t u = g.u[k][q];
+            const uint32_t ul = u - rbase;
+            const uint32_t bit = 1u << (u & 31);
+            if (!(lds[ul >> 5] & bit)) {
+              const uint32_t old = atomicOr(&lds[ul >> 5], bit);
+              if (!(old & bit)) p.mark[u] = 1;
+            }
+          }
+        }
+    }
+  }
+}
+
 // Stage 2 of the lazy scheme: coalesced sweep over 32-vertex words, one word per
-// thread.  Queue space is reserved once per workgroup (wavefront scans, then one
+// thread: the word's 32 reached bytes (a 32-byte load) against its visited bits.  Queue space is reserved once per workgroup (wavefront scans, then one
 // atomic add by thread 0): a reservation per wavefront would put thousands of
 // atomics on one counter per level.
 template <int SIG>
@@ -175,10 +254,21 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, ui
     const uint32_t t = b0 + threadIdx.x;
     uint32_t cnt = 0, pushmask = 0;
     if (t < p.n_words) {
-      const uint2 cv = reinterpret_cast<const uint2*>(p.vis)[t];
-      const uint32_t diff = cv.x ^ cv.y;
+      // the 32 reached bytes of word t, folded into one bit each
+      const uint4* mb = reinterpret_cast<const uint4*>(p.mark + 32ull * t);
+      const uint4 m0 = mb[0], m1 = mb[1];
+      const uint32_t mw[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+      uint32_t reached = 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint32_t x = mw[i];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) reached |= ((x >> (8 * b)) & 0xFFu) ? (1u << (4 * i + b)) : 0u;
+      }
+      const uint32_t cur = p.vis[t];
+      const uint32_t diff = reached & ~cur;
       if (diff) {
-        p.vis[2 * t] = cv.y;
+        p.vis[t] = cur | diff;
         p.front[t] = diff;
         uint32_t d = diff;
         while (d) {
@@ -209,12 +299,8 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, ui
       s_base = run ? atomicAdd(qlen, run) : 0u;
     }
     __syncthreads();
-    uint32_t pos = s_base + s_wave[wave] + incl - cnt;
-    if (cnt != 0) {
-#pragma unroll
-      for (int i = 0; i < SPW; ++i)
-        if (pushmask & (1u << i)) pos = push_set(p, qn, pos, t * SPW + i);
-    }
+    const uint32_t pos = s_base + s_wave[wave] + incl - cnt;
+    wave_push<SPW>(p.real_ptrs, qn, pos, cnt, pushmask, [&](int i) { return t * SPW + i; }, RangeEntry{p.vss_range});
     __syncthreads();
   }
 }
@@ -260,14 +346,10 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
         }
       }
     uint32_t total;
-    uint32_t pos = wave_reserve(qlen, cnt, total);
-    if (total != 0 && cnt != 0) {
-#pragma unroll
-      for (int k = 0; k < G; ++k)
-#pragma unroll
-        for (int r = 0; r < SLOTS; ++r)
-          if (pushmask & (1u << (k * SLOTS + r))) pos = push_set(p, qn, pos, g.u[k][r] / SIG);
-    }
+    const uint32_t pos = wave_reserve(qlen, cnt, total);
+    if (total != 0)
+      wave_push<G * SLOTS>(p.real_ptrs, qn, pos, cnt, pushmask, [&](int i) { return g.u[i / SLOTS][i % SLOTS] / SIG; },
+                           RangeEntry{p.vss_range});
   });
 }
 
@@ -277,15 +359,16 @@ __device__ __forceinline__ void clear_chunks(const BfsParams& p, uint32_t* f, co
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nt = gridDim.x * blockDim.x;
   for (uint32_t i = tid; i < len; i += nt) {
-    const uint32_t ss = p.v2r[qold[i]];
+    const uint32_t ss = p.v2r[qold[i] >> kRangeBits];
     if (SIG == 8) reinterpret_cast<uint8_t*>(f)[ss] = 0;
     else if (SIG == 16) reinterpret_cast<uint16_t*>(f)[ss] = 0;
     else f[ss] = 0;
   }
 }
 
-template <typename MT, int SLOTS, bool LAZY, int G>
+template <typename MT, int SLOTS, bool LAZY, int G, bool LDSVIS>
 __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
+  extern __shared__ uint32_t lds_vis[];
   constexpr int SIG = 8 * sizeof(MT);
   uint32_t* ctrl = p.ctrl;
   uint32_t* qlen = ctrl + kQlen;  // qlen[i] at qlen[i * kLine]
@@ -301,9 +384,14 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
   if (LAZY) {
     for (uint32_t t = tid; t < p.n_words; t += nt) {
       const uint32_t b = (t == sw) ? sbit : 0u;
-      p.vis[2 * t] = b;
-      p.vis[2 * t + 1] = b;
+      p.vis[t] = b;
       p.front[t] = b;
+      // the word's 32 reached bytes: zero, except the source's
+      uint32_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (t == sw) z[(p.src & 31) >> 2] = 1u << (8 * (p.src & 3));
+      uint4* mb = reinterpret_cast<uint4*>(p.mark + 32ull * t);
+      mb[0] = make_uint4(z[0], z[1], z[2], z[3]);
+      mb[1] = make_uint4(z[4], z[5], z[6], z[7]);
     }
   } else {
     for (uint32_t t = tid; t < p.n_words; t += nt) {
@@ -314,7 +402,7 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
       p.front[2 * p.n_words + t] = 0;
     }
   }
-  for (uint32_t j = tid; j < q0n; j += nt) p.queue[j] = q0b + j;
+  for (uint32_t j = tid; j < q0n; j += nt) p.queue[j] = RangeEntry{p.vss_range}(q0b + j);
   if (tid == 0) {
     qlen[0] = q0n;
     qlen[kLine] = 0;
@@ -330,7 +418,10 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
       const uint32_t len = ld_relaxed(qlen + ((level - 1) % 3) * kLine);
       uint32_t* qnext_len = qlen + (level % 3) * kLine;
       if (tid == 0) __hip_atomic_store(qlen + ((level + 1) % 3) * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      stage1_lazy<MT, SLOTS, G>(p, qc, len);
+      if (LDSVIS)
+        stage1_lazy_lds<MT, SLOTS, G>(p, qc, len, lds_vis);
+      else
+        stage1_lazy<MT, SLOTS, G>(p, qc, len);
       grid_barrier(ctrl);
       stage2_lazy<SIG>(p, qn, qnext_len, level);
       grid_barrier(ctrl);
@@ -385,45 +476,51 @@ __global__ void parents_scan(BfsParams p, const int32_t* __restrict__ levels, in
   }
 }
 
-template <typename MT, int SLOTS, bool LAZY>
+template <typename MT, int SLOTS, bool LAZY, bool LDSVIS>
 const void* sym_group(uint32_t group) {
   switch (group) {
-    case 1: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 1>);
-    case 2: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 2>);
-    case 4: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 4>);
+    case 1: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 1, LDSVIS>);
+    case 2: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 2, LDSVIS>);
+    case 4: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 4, LDSVIS>);
     default: return nullptr;
   }
 }
 
 template <typename MT>
-const void* sym_slots(uint32_t slots, bool lazy, uint32_t group) {
+const void* sym_slots(uint32_t slots, bool lazy, uint32_t group, bool lds) {
+  // the LDS-visited variant exists for the lazy scheme only
   switch (slots) {
-    case 1: return lazy ? sym_group<MT, 1, true>(group) : sym_group<MT, 1, false>(group);
-    case 2: return lazy ? sym_group<MT, 2, true>(group) : sym_group<MT, 2, false>(group);
-    case 4: return lazy ? sym_group<MT, 4, true>(group) : sym_group<MT, 4, false>(group);
-    case 8: return lazy ? sym_group<MT, 8, true>(group) : sym_group<MT, 8, false>(group);
+    case 1: return lazy ? (lds ? sym_group<MT, 1, true, true>(group) : sym_group<MT, 1, true, false>(group))
+                        : sym_group<MT, 1, false, false>(group);
+    case 2: return lazy ? (lds ? sym_group<MT, 2, true, true>(group) : sym_group<MT, 2, true, false>(group))
+                        : sym_group<MT, 2, false, false>(group);
+    case 4: return lazy ? (lds ? sym_group<MT, 4, true, true>(group) : sym_group<MT, 4, true, false>(group))
+                        : sym_group<MT, 4, false, false>(group);
+    case 8: return lazy ? (lds ? sym_group<MT, 8, true, true>(group) : sym_group<MT, 8, true, false>(group))
+                        : sym_group<MT, 8, false, false>(group);
     default: return nullptr;
   }
 }
 
 }  // namespace
 
-const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy, uint32_t group) {
+const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, bool lds) {
   switch (sigma) {
-    case 8: return sym_slots<uint8_t>(slots, lazy, group);
-    case 16: return sym_slots<uint16_t>(slots, lazy, group);
-    case 32: return sym_slots<uint32_t>(slots, lazy, group);
+    case 8: return sym_slots<uint8_t>(slots, lazy, group, lds);
+    case 16: return sym_slots<uint16_t>(slots, lazy, group, lds);
+    case 32: return sym_slots<uint32_t>(slots, lazy, group, lds);
     default: return nullptr;
   }
 }
 
 hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, uint32_t grid,
                       uint32_t block, hipStream_t stream) {
-  const void* k = bfs_kernel_symbol(sigma, slots, lazy, group);
-  if (!k) return hipErrorInvalidValue;
+  const bool lds = lazy && p.range_words > 0;
+  const void* k = bfs_kernel_symbol(sigma, slots, lazy, group, lds);
+  if (!k || grid % p.nranges != 0) return hipErrorInvalidValue;
   BfsParams copy = p;
   void* args[] = {&copy};
-  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(block), args, 0, stream);
+  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(block), args, lds ? 4 * p.range_words : 0, stream);
 }
 
 hipError_t launch_parents(const BfsParams& p, uint32_t sigma, const int32_t* levels, int32_t* parents,

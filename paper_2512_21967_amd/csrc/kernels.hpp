@@ -24,24 +24,36 @@ struct BfsParams {
   const uint32_t* v2r;
   const uint32_t* real_ptrs;
   const uint32_t* orig_id;  // new label -> original ID; nullptr = identity
+  const uint8_t* vss_range; // row range of each VSS
   // per-call workspace
-  uint32_t* vis;            // lazy: 2 * n_words (current/next interleaved); eager: n_words
+  uint32_t* vis;            // visited bits, n_words
+  uint8_t* mark;            // lazy: reached byte per vertex, 32 * n_words
   uint32_t* front;          // lazy: n_words; eager: 3 * n_words
   uint32_t* queue;          // 3 * qcap
   uint32_t* ctrl;           // kCtrlWords
   int32_t* levels;          // n, original IDs
   uint32_t n, n_words, num_sets, num_vss, qcap;
   uint32_t src;             // source, new label
+  uint32_t nranges;         // row ranges (a power of two, at most kMaxRanges)
+  uint32_t range_len;       // rows per range (a multiple of 32)
+  uint32_t range_words;     // visited words of one range held in LDS (0: none)
 };
 
+// Queue entries carry the VSS's row range in their low bits.
+constexpr uint32_t kRangeBits = 5;
+constexpr uint32_t kMaxRanges = 1u << kRangeBits;
+constexpr uint32_t kMaxLdsRangeBytes = 64 * 1024;
+
 // Persistent single-source BFS; lazy selects Algorithm 3, otherwise Algorithm 2.
-// grid must be co-resident (the call uses a cooperative launch).
-// group = VSSs whose slice loads a wavefront keeps in flight together (1, 2, 4).
+// grid must be co-resident (the call uses a cooperative launch) and a multiple of
+// p.nranges.  group = VSSs whose slice loads a wavefront keeps in flight together
+// (1, 2, 4).  With p.range_words > 0 the lazy kernel keeps the visited bits of
+// each workgroup's row range in LDS (4 * range_words bytes of dynamic LDS).
 hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, uint32_t grid,
                       uint32_t block, hipStream_t stream);
 
 // Returns the kernel symbol used by launch_bfs (for occupancy queries).
-const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy, uint32_t group);
+const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, bool lds);
 
 // k-source BFS (k <= 64): per-vertex 64-bit frontier and visited words, bit j for
 // source j.

@@ -126,15 +126,8 @@ __global__ __launch_bounds__(kManyBlock) void bfs_many_kernel(const ManyItem* __
         s_qlen[level & 1] += run;
       }
       __syncthreads();
-      if (cnt) {
-        uint32_t pos = s_base + s_wave[wave] + incl - cnt;
-#pragma unroll
-        for (int i = 0; i < SPW; ++i)
-          if (pushmask & (1u << i)) {
-            const uint32_t s = t * SPW + i;
-            for (uint32_t v = it.real_ptrs[s]; v < it.real_ptrs[s + 1]; ++v) qn[pos++] = v;
-          }
-      }
+      const uint32_t pos = s_base + s_wave[wave] + incl - cnt;
+      wave_push<SPW>(it.real_ptrs, qn, pos, cnt, pushmask, [&](int i) { return t * SPW + i; });
       __syncthreads();
     }
     // queue entries written by other waves must be visible before Stage 1 reads them

@@ -123,11 +123,8 @@ __device__ __forceinline__ void multi_stage2(const MultiParams& p, uint32_t* qn,
       s_base = run ? atomicAdd(qlen, run) : 0u;
     }
     __syncthreads();
-    if (cnt) {
-      uint32_t pos = s_base + s_wave[wave] + incl - cnt;
-      const uint32_t ss = u / SIG;
-      for (uint32_t v = p.real_ptrs[ss]; v < p.real_ptrs[ss + 1]; ++v) qn[pos++] = v;
-    }
+    const uint32_t pos = s_base + s_wave[wave] + incl - cnt;
+    wave_push<1>(p.real_ptrs, qn, pos, cnt, cnt ? 1u : 0u, [&](int) { return u / SIG; });
     __syncthreads();
   }
 }

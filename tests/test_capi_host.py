@@ -73,7 +73,7 @@ def test_graph_validation_errors():
     assert L.blest_build(1, 0, None, None, ctypes.byref(o), ctypes.byref(h)) == 1
     assert L.blest_build(1, 0, blest._p32(rp), blest._p32(col), ctypes.byref(o), None) == 1
     for field, bad in (("sigma", 12), ("slots", 3), ("window", 12), ("reorder", 9), ("update", -1), ("block", 100),
-                       ("group", 3), ("blocks_per_cu", 2)):
+                       ("group", 3), ("blocks_per_cu", 2), ("ranges", 3), ("ranges", 64)):
         o = blest.default_options()
         o.device = -1
         setattr(o, field, bad)
@@ -128,7 +128,8 @@ def check_bvss_against_oracle(gr, g, sigma, slots):
     sid, row, mask = obvss.slices(h, sigma)
     n_sets = obvss.num_slice_sets(h.n, sigma)
     tau = 64 * slots
-    part = obvss.vss_partition(sid, row, mask, n_sets, tau)
+    st = g.stats()
+    part = obvss.vss_partition(sid, row, mask, n_sets, tau, st["range_len"] if st["nranges"] > 1 else None)
     rp = g.export("real_ptrs")
     v2r = g.export("virtual_to_real")
     beg = g.export("vss_begin")
@@ -144,12 +145,13 @@ def check_bvss_against_oracle(gr, g, sigma, slots):
     for v, (r, m) in enumerate(part["groups"]):
         np.testing.assert_array_equal(rows[beg[v]:beg[v + 1]], r)
         np.testing.assert_array_equal(mvals[beg[v]:beg[v + 1]], m)
-    st = g.stats()
+    np.testing.assert_array_equal(g.export("vss_range"), part["blocks"])
     assert st["num_slices"] == len(sid) and st["num_vss"] == len(v2r) and st["tau"] == tau
     assert st["compression"] == pytest.approx(obvss.compression_ratio(h.nnz, len(sid), sigma))
     paper_groups = obvss.vss_partition(sid, row, mask, n_sets, 32 * (32 // sigma))["groups"]
     assert st["u_div_paper"] == pytest.approx(obvss.update_divergence(paper_groups, 32), rel=1e-9, abs=1e-9)
     assert st["u_div_native"] == pytest.approx(obvss.update_divergence(part["groups"], 64), rel=1e-9, abs=1e-9)
+    assert st["nranges"] >= 1 and st["range_len"] % 32 == 0
     assert st["bvss_bytes_table3"] == obvss.bvss_bytes_table3(len(sid), len(v2r), n_sets, sigma)
 
 
@@ -167,6 +169,27 @@ def test_bvss_matches_oracle_directed_and_ragged():
         gr = inputs.from_arcs(n, rng.integers(0, n, m), rng.integers(0, n, m), False)
         g = host_graph(gr, sigma=8, slots=1, reorder="none")
         check_bvss_against_oracle(gr, g, 8, 1)
+
+
+@pytest.mark.parametrize("ranges", [2, 8, 32])
+def test_bvss_row_ranges_match_oracle(ranges):
+    gr = inputs.rmat_workload(12, 16, seed=ranges, permute_seed=5)
+    g = host_graph(gr, sigma=8, slots=2, reorder="none", update="lazy", ranges=ranges)
+    st = g.stats()
+    assert st["nranges"] == ranges and st["range_len"] * ranges >= gr.n
+    check_bvss_against_oracle(gr, g, 8, 2)
+    # every VSS pulls rows of its own range only
+    beg, rows, rng = g.export("vss_begin"), g.export("row_ids"), g.export("vss_range")
+    for v in range(len(rng)):
+        assert np.all(rows[beg[v]:beg[v + 1]] // st["range_len"] == rng[v])
+
+
+def test_auto_ranges_follow_the_update_scheme():
+    gr = inputs.rmat_workload(20, 8, seed=1, permute_seed=2)
+    lazy = host_graph(gr, reorder="none", update="lazy").stats()
+    eager = host_graph(gr, reorder="none", update="eager").stats()
+    # 2^20 vertices = 128 KB of visited bits: two 64 KB ranges for the lazy kernel
+    assert lazy["nranges"] == 2 and eager["nranges"] == 1
 
 
 @pytest.mark.parametrize("reorder", ["compression", "bandwidth"])

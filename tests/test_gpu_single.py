@@ -148,3 +148,34 @@ def test_full_size_s16_config():
     for update in ("eager", "lazy"):
         g = blest.Graph(gr, reorder="none", update=update)
         check_sources(gr, g, inputs.sources(gr, seed=1, k=3))
+
+
+@pytest.mark.parametrize("ranges", [1, 2, 8, 32])
+@pytest.mark.parametrize("update", ["lazy", "eager"])
+def test_row_ranges(ranges, update):
+    """VSSs cut at row-range boundaries; the lazy kernel keeps each workgroup's
+    range of visited bits in LDS."""
+    gr = inputs.rmat_workload(14, 16, seed=ranges, permute_seed=3)
+    g = blest.Graph(gr, update=update, reorder="none", ranges=ranges)
+    assert g.stats()["nranges"] == ranges
+    check_sources(gr, g, inputs.sources(gr, seed=ranges, k=3))
+
+
+def test_lazy_without_lds_bitmap():
+    """A graph whose visited bitmap does not fit one LDS range, forced to one range:
+    the lazy kernel checks visited bits in global memory."""
+    gr = inputs.rmat_workload(20, 4, seed=2, permute_seed=1)
+    g = blest.Graph(gr, update="lazy", reorder="none", ranges=1)
+    check_sources(gr, g, inputs.sources(gr, seed=1, k=2))
+    g.configure(update="eager")
+    check_sources(gr, g, inputs.sources(gr, seed=2, k=1))
+
+
+def test_full_size_s22_config_sampled_sources():
+    """R-MAT scale 22, edge factor 16, labels permuted, Algorithm 1 ordering: the
+    benchmark configuration, in its default launch shape, on sampled sources."""
+    gr = inputs.rmat_workload(22, 16, seed=1, permute_seed=2)
+    g = blest.Graph(gr, reorder="compression")
+    st = g.stats()
+    assert st["update_used"] == "lazy" and st["nranges"] == 8
+    check_sources(gr, g, inputs.sources(gr, seed=3, k=64)[:2])
