@@ -186,13 +186,17 @@ enum {
 blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t capacity_bytes,
                           uint64_t* size_bytes);
 
-/* Algorithmic device bytes of one BFS whose result is `levels` (HOST int32[n],
- * original IDs): for every level l and every slice set holding a vertex of level
- * l - 1, its unpadded slices (4-byte row ID + sigma/8-byte mask), its frontier
- * chunk and 8 bytes per VSS (queue entry + VSS metadata); plus the per-level
- * bitmap sweeps of the lazy scheme (2 * n/8 bytes per level) and the 4n-byte
- * level initialisation.  Lets a benchmark turn a measured time into GB/s. */
-blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint64_t* bytes);
+/* Algorithmic device bytes of one BFS call whose result is `levels` (HOST int32,
+ * k rows of n in original IDs, k = 1 for blest_bfs, 1..64 for blest_bfs_multi):
+ * for every iteration l and every slice set holding a vertex of level l - 1 in any
+ * row, its unpadded slices (4-byte row ID + sigma/8-byte mask), its frontier (the
+ * sigma-bit chunk, or sigma 64-bit words when k > 1) and 8 bytes per VSS (queue
+ * entry + VSS metadata); plus, for k = 1, the lazy scheme's per-level sweep of the
+ * two n-bit visited bitmaps and the 4n-byte level initialisation; for k > 1 a
+ * 24n-byte vertex sweep per level, the 4kn-byte initialisation and 4 bytes per
+ * reached (source, vertex) pair.  Lets a benchmark turn a measured time into GB/s.
+ * Errors: INVALID_ARGUMENT. */
+blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k, uint64_t* bytes);
 
 /* Releases the handle and its device memory.  NULL is ignored.  Must not be called
  * while work using the handle is still pending on a stream. */

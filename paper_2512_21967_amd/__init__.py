@@ -91,7 +91,7 @@ def lib():
     L.blest_footprint.restype = ctypes.c_int
     L.blest_export.argtypes = [vp, i32, vp, u64, ctypes.POINTER(u64)]
     L.blest_export.restype = ctypes.c_int
-    L.blest_model_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(u64)]
+    L.blest_model_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), u32, ctypes.POINTER(u64)]
     L.blest_model_bytes.restype = ctypes.c_int
     L.blest_destroy.argtypes = [vp]
     L.blest_destroy.restype = None
@@ -236,13 +236,14 @@ class Graph:
         return out[: size.value // np.dtype(dt).itemsize]
 
     def model_bytes(self, levels) -> int:
+        """Algorithmic bytes of the call that produced `levels` ([n] or [k, n])."""
         lv = np.ascontiguousarray(levels, dtype=np.int32)
-        if lv.size != self.n:
-            raise ValueError("levels must hold n entries")
+        if lv.size % self.n != 0 or lv.size == 0:
+            raise ValueError("levels must hold k * n entries")
         b = ctypes.c_uint64()
         _check("blest_model_bytes", lib().blest_model_bytes(self.handle,
                                                             lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                                            ctypes.byref(b)))
+                                                            lv.size // self.n, ctypes.byref(b)))
         return int(b.value)
 
 

@@ -89,6 +89,7 @@ struct blest_graph {
   std::map<void*, std::unique_ptr<MultiWorkspace>> multi_ws;
   uint32_t multi_grid = 0;
   uint32_t n_words() const { return (n + 31) / 32; }
+  uint32_t orig_id_of(uint32_t u) const { return identity ? u : orig_id[u]; }
 };
 
 // A device-resident table of (graph, source, output) items for the many-graphs
@@ -672,36 +673,62 @@ blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t cap
   return BLEST_OK;
 }
 
-blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint64_t* bytes) {
-  if (!h || !levels || !bytes) return BLEST_ERR_INVALID_ARGUMENT;
+blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k, uint64_t* bytes) {
+  if (!h || !levels || !bytes || k == 0 || k > 64) return BLEST_ERR_INVALID_ARGUMENT;
   const Bvss& b = h->bvss;
-  // Deepest level and, per slice set, the set of levels present among its vertices.
+  const uint32_t n = h->n;
+  // Deepest level over all rows; per slice set, the distinct levels present among
+  // its vertices in any row (the set is active at iteration l + 1 for each).
   int32_t maxl = 0;
-  for (uint32_t v = 0; v < h->n; ++v) maxl = std::max(maxl, levels[v]);
-  uint64_t total = 0;
-  std::vector<int32_t> lv(h->n);
-  for (uint32_t v = 0; v < h->n; ++v) lv[h->new_id[v]] = levels[v];
+  uint64_t reached = 0;
+  for (uint64_t i = 0; i < (uint64_t)k * n; ++i) {
+    maxl = std::max(maxl, levels[i]);
+    reached += levels[i] >= 0;
+  }
+  std::vector<uint64_t> lvmask(n, 0);  // bit l: some row has this vertex at level l (l < 64)
+  std::vector<uint8_t> deep(n, 0);     // levels >= 64 tracked exactly below
+  for (uint32_t j = 0; j < k; ++j)
+    for (uint32_t v = 0; v < n; ++v) {
+      const int32_t l = levels[(uint64_t)j * n + v];
+      if (l < 0) continue;
+      if (l < 64) lvmask[h->new_id[v]] |= 1ull << l;
+      else deep[h->new_id[v]] = 1;
+    }
   const uint64_t per_slice = 4 + b.sigma / 8;
+  const uint64_t front = k == 1 ? b.sigma / 8 : 8ull * b.sigma;  // frontier chunk / frontier words of a set
+  uint64_t total = 0;
+  std::vector<int32_t> seen;
   for (uint32_t s = 0; s < b.num_sets; ++s) {
     const uint32_t nv = b.real_ptrs[s + 1] - b.real_ptrs[s];
     if (nv == 0) continue;
     const uint64_t slices = b.set_beg[s + 1] - b.set_beg[s];
-    // the set is active at iteration l + 1 for each distinct level l of its vertices
-    int32_t seen[64];
-    int ns = 0;
-    const uint32_t v0 = s * b.sigma, v1 = std::min<uint32_t>(h->n, v0 + b.sigma);
+    const uint32_t v0 = s * b.sigma, v1 = std::min<uint32_t>(n, v0 + b.sigma);
+    uint64_t m = 0;
+    bool any_deep = false;
     for (uint32_t v = v0; v < v1; ++v) {
-      int32_t l = lv[v];
-      if (l < 0) continue;
-      bool dup = false;
-      for (int i = 0; i < ns; ++i) dup |= seen[i] == l;
-      if (!dup) seen[ns++] = l;
+      m |= lvmask[v];
+      any_deep |= deep[v] != 0;
     }
-    total += (uint64_t)ns * (slices * per_slice + b.sigma / 8 + 8ull * nv);
+    uint64_t acts = (uint64_t)__builtin_popcountll(m);
+    if (any_deep) {  // rare: levels >= 64 (high-diameter graphs), counted exactly
+      seen.clear();
+      for (uint32_t j = 0; j < k; ++j)
+        for (uint32_t v = v0; v < v1; ++v) {
+          const int32_t l = levels[(uint64_t)j * n + h->orig_id_of(v)];
+          if (l >= 64 && std::find(seen.begin(), seen.end(), l) == seen.end()) seen.push_back(l);
+        }
+      acts += seen.size();
+    }
+    total += acts * (slices * per_slice + front + 8ull * nv);
   }
   const uint64_t iters = (uint64_t)maxl + 1;
-  if (h->lazy) total += iters * 2ull * ((h->n + 7) / 8);
-  total += 4ull * h->n;
+  if (k == 1) {
+    if (h->lazy) total += iters * 2ull * ((n + 7) / 8);  // Stage 2 reads both visited bitmaps
+    total += 4ull * n;                                      // level initialisation
+  } else {
+    total += iters * 24ull * n;                            // vertex sweep: visited pair + frontier word
+    total += 4ull * k * n + 4ull * reached;                // level initialisation + level writes
+  }
   *bytes = total;
   return BLEST_OK;
 }
