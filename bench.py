@@ -20,8 +20,6 @@ bounded sample of the same work.
 from __future__ import annotations
 
 import argparse
-import glob
-import hashlib
 import json
 import os
 import sys
@@ -38,18 +36,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2512_21967_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".hpp", ".cpp")):
-            with open(f, "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profiles(key):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs, if
     they were taken on the current kernel sources."""
+    from paper_2512_21967_amd.profsum import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None

@@ -77,10 +77,19 @@ typedef struct {
   uint32_t block;      /* threads per workgroup of the persistent kernels, a multiple of 64 (0 = 1024) */
   uint32_t blocks_per_cu; /* persistent workgroups per compute unit (0 = 1); block * blocks_per_cu <= 1024 */
   uint32_t group;      /* VSSs whose slice loads a wavefront keeps in flight: 1, 2 or 4 (0 = 2) */
-  uint32_t ranges;     /* row ranges of the LDS-resident visited bits of the lazy kernel: a power of
-                          two <= 32; every VSS also stays inside one range (0 = auto: split only
-                          for the lazy scheme, into the fewest ranges whose bitmap fits 64 KB) */
+  uint32_t ranges;     /* row ranges of the lazy kernel: a power of two <= 32 (0 = 1).  With R > 1
+                          every VSS stays inside one range and workgroup b caches the visited bits
+                          of range b % R; one range (the default) caches the lowest rows */
+  uint32_t hubs;       /* hub sort after the ordering: sigma-aligned vertex groups reordered by
+                          summed in-degree, largest first, groups kept intact (compression is
+                          unchanged); 0 = auto (on for social-like graphs), 1 = off, 2 = on */
+  uint32_t lds_kib;    /* LDS per workgroup caching visited bits in the lazy Stage 1, in KiB:
+                          0 = auto (128, clamped to the device), 1..128, or BLEST_LDS_OFF.  The
+                          cache holds the first C words (C a power of two) of every 64-word
+                          chunk of the range, C as large as fits */
 } blest_options;
+
+#define BLEST_LDS_OFF 0xFFFFFFFFu
 
 typedef struct {
   uint32_t n;
@@ -101,6 +110,10 @@ typedef struct {
   uint64_t bvss_bytes_table3;   /* the paper's accounting (Table 3) for this structure */
   double reorder_seconds;       /* host ordering time */
   double build_seconds;         /* host BVSS construction time (after ordering) */
+  int32_t hubs_sorted;          /* 1 if the hub sort was applied */
+  uint32_t lds_bytes;           /* visited bits per workgroup cached in LDS by the lazy kernel */
+  uint32_t lds_chunk_words;     /* cached words per 64-word chunk of a range (64 = the whole range) */
+  uint32_t hub_cpos;            /* positions per 64-word chunk that the hub sort filled first (0: none) */
 } blest_stats_t;
 
 /* Fills *opt with the defaults listed above. */
@@ -181,7 +194,9 @@ enum {
   BLEST_EXPORT_VSS_BEGIN = 3,       /* uint32[num_vss + 1]: first slice of each VSS */
   BLEST_EXPORT_ROW_IDS = 4,         /* uint32[num_slices], new labels */
   BLEST_EXPORT_MASKS = 5,           /* sigma/8 bytes per slice, little-endian, bit j = column j */
-  BLEST_EXPORT_VSS_RANGE = 6        /* uint8[num_vss]: row range of each VSS */
+  BLEST_EXPORT_VSS_RANGE = 6,       /* uint8[num_vss]: row range of each VSS */
+  BLEST_EXPORT_ORDER_ID = 7         /* uint32[n]: label of each original vertex after the ordering
+                                       alone (Algorithm 1 or RCM), before the hub sort */
 };
 blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t capacity_bytes,
                           uint64_t* size_bytes);

@@ -21,9 +21,11 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "invalid graph", 3: "too large", 4:
           5: "budget", 6: "device error", 7: "no device", 8: "internal error"}
 REORDER = {"auto": 0, "none": 1, "compression": 2, "bandwidth": 3}
 UPDATE = {"auto": 0, "eager": 1, "lazy": 2}
+HUBS = {"auto": 0, "off": 1, "on": 2}
+LDS_OFF = 0xFFFFFFFF
 EXPORT = {"new_id": (0, np.uint32), "real_ptrs": (1, np.uint32), "virtual_to_real": (2, np.uint32),
           "vss_begin": (3, np.uint32), "row_ids": (4, np.uint32), "masks": (5, np.uint8),
-          "vss_range": (6, np.uint8)}
+          "vss_range": (6, np.uint8), "order_id": (7, np.uint32)}
 EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_bfs_multi", "blest_bfs_many",
                     "blest_batch_create", "blest_batch_run", "blest_batch_destroy", "blest_configure", "blest_stats", "blest_footprint", "blest_export", "blest_model_bytes", "blest_destroy",
                     "blest_status_string")
@@ -39,7 +41,8 @@ class Options(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("window", ctypes.c_uint32),
                 ("reorder", ctypes.c_int32), ("update", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("threads", ctypes.c_uint32), ("block", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
-                ("group", ctypes.c_uint32), ("ranges", ctypes.c_uint32)]
+                ("group", ctypes.c_uint32), ("ranges", ctypes.c_uint32), ("hubs", ctypes.c_uint32),
+                ("lds_kib", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -50,7 +53,9 @@ class Stats(ctypes.Structure):
                 ("social_like", ctypes.c_int32), ("reorder_used", ctypes.c_int32), ("update_used", ctypes.c_int32),
                 ("nranges", ctypes.c_uint32), ("range_len", ctypes.c_uint32),
                 ("bvss_device_bytes", ctypes.c_uint64), ("bvss_bytes_table3", ctypes.c_uint64),
-                ("reorder_seconds", ctypes.c_double), ("build_seconds", ctypes.c_double)]
+                ("reorder_seconds", ctypes.c_double), ("build_seconds", ctypes.c_double),
+                ("hubs_sorted", ctypes.c_int32), ("lds_bytes", ctypes.c_uint32),
+                ("lds_chunk_words", ctypes.c_uint32), ("hub_cpos", ctypes.c_uint32)]
 
 
 _lib = None
@@ -138,12 +143,13 @@ class Graph:
     and exports work; BFS calls raise)."""
 
     def __init__(self, csr, *, sigma=8, slots=4, window=1 << 16, reorder="auto", update="auto",
-                 device=0, threads=0, block=0, blocks_per_cu=0, group=0, ranges=0):
+                 device=0, threads=0, block=0, blocks_per_cu=0, group=0, ranges=0, hubs="auto", lds_kib=0):
         o = default_options()
         o.sigma, o.slots, o.window = sigma, slots, window
         o.reorder, o.update = REORDER[reorder], UPDATE[update]
         o.device, o.threads, o.block, o.blocks_per_cu = device, threads, block, blocks_per_cu
-        o.group, o.ranges = group, ranges
+        o.group, o.ranges, o.hubs = group, ranges, HUBS[hubs]
+        o.lds_kib = LDS_OFF if lds_kib is None else lds_kib
         rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint32)
         col = np.ascontiguousarray(csr.col if len(csr.col) else np.zeros(1, np.uint32), dtype=np.uint32)
         h = ctypes.c_void_p()

@@ -61,6 +61,11 @@ struct DeviceSerial {
 };
 DeviceSerial g_serial[64];
 
+// Lazy levels with fewer queued VSSs than min(kLdsMinQueue, cached words / 16)
+// check visited bits in memory only: refilling the LDS cache costs about as much
+// as such a level's checks.
+constexpr uint32_t kLdsMinQueue = 4096;
+
 }  // namespace
 
 struct blest_batch;
@@ -71,10 +76,12 @@ struct blest_graph {
   uint64_t m = 0;
   Bvss bvss;
   std::vector<uint32_t> new_id;   // original -> new
+  std::vector<uint32_t> order_id; // original -> label after the ordering alone (before the hub sort)
   std::vector<uint32_t> orig_id;  // new -> original
   bool identity = true;
   bool lazy = false;
   int social = 0;
+  int hubs_sorted = 0;
   int reorder_used = BLEST_REORDER_NONE;
   double u_div_paper = 0, u_div_native = 0, compression = 0;
   double reorder_seconds = 0, build_seconds = 0;
@@ -83,6 +90,7 @@ struct blest_graph {
   int device = -1;
   DevBuf d_row_ids, d_masks, d_vss_beg, d_v2r, d_real_ptrs, d_orig_id, d_vss_range;
   uint32_t nranges = 1, range_len = 0, range_words = 0;
+  uint32_t lds_cap_words = 0, lds_cshift = 0, hub_cpos = 0;
   uint32_t grid = 0, block = 0;
   std::mutex ws_mu;
   std::map<void*, std::unique_ptr<SingleWorkspace>> single_ws;
@@ -137,6 +145,8 @@ bool valid_options(const blest_options& o) {
   if ((uint64_t)o.block * (o.blocks_per_cu ? o.blocks_per_cu : 1) > 1024) return false;
   if (o.group != 1 && o.group != 2 && o.group != 4) return false;
   if (o.ranges > kMaxRanges || (o.ranges & (o.ranges - 1)) != 0) return false;
+  if (o.hubs > 2) return false;
+  if (o.lds_kib != BLEST_LDS_OFF && o.lds_kib > kMaxLdsBytes / 1024) return false;
   return true;
 }
 
@@ -159,7 +169,12 @@ blest_status to_device(blest_graph* g) {
   if (e == hipSuccess) e = upload(g->d_vss_beg, b.vss_beg);
   if (e == hipSuccess) e = upload(g->d_v2r, b.v2r);
   if (e == hipSuccess) e = upload(g->d_real_ptrs, b.real_ptrs);
-  if (e == hipSuccess && !g->identity) e = upload(g->d_orig_id, g->orig_id);
+  if (e == hipSuccess && !g->identity) {
+    // padded to whole 32-vertex words: the lazy kernel loads a word's IDs as vectors
+    std::vector<uint32_t> padded(g->orig_id);
+    padded.resize(32ull * g->n_words(), 0u);
+    e = upload(g->d_orig_id, padded);
+  }
   if (e == hipSuccess) e = upload(g->d_vss_range, b.vss_range);
   if (e == hipErrorOutOfMemory) return BLEST_ERR_OUT_OF_MEMORY;
   if (e != hipSuccess) return BLEST_ERR_DEVICE;
@@ -176,18 +191,29 @@ blest_status set_grid(blest_graph* g) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess || cus <= 0)
     return BLEST_ERR_DEVICE;
   g->block = g->opt.block;
-  uint32_t per_cu = UINT32_MAX;
-  for (int lazy = 0; lazy < 2; ++lazy) {
-    int nb = 0;
-    const bool lds = lazy && g->range_words > 0;
-    const void* k = bfs_kernel_symbol(b.sigma, b.slots, lazy != 0, g->opt.group, lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)g->block, lds ? 4 * g->range_words : 0) !=
-            hipSuccess ||
-        nb <= 0)
+  const bool lds = g->lazy && g->range_words > 0;
+  const void* k = bfs_kernel_symbol(b.sigma, b.slots, g->lazy, g->opt.group, lds);
+  if (lds) {
+    // the LDS cache takes what the device leaves beside the kernel's static LDS
+    int max_lds = 0;
+    hipFuncAttributes fa{};
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device) != hipSuccess ||
+        hipFuncGetAttributes(&fa, k) != hipSuccess)
       return BLEST_ERR_DEVICE;
-    per_cu = std::min<uint32_t>(per_cu, (uint32_t)nb);
+    const int64_t room = ((int64_t)max_lds - (int64_t)fa.sharedSizeBytes) / 4;
+    if (room < 1) return BLEST_ERR_DEVICE;
+    g->range_words = cache_shape(g->range_len / 32, std::min<uint32_t>(g->lds_cap_words, (uint32_t)room),
+                                 g->lds_cshift);
+    if (g->range_words == 0) return BLEST_ERR_DEVICE;
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * g->range_words)) != hipSuccess)
+      return BLEST_ERR_DEVICE;
   }
-  per_cu = std::min<uint32_t>(per_cu, g->opt.blocks_per_cu);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)g->block, lds ? 4 * g->range_words : 0) !=
+          hipSuccess ||
+      nb <= 0)
+    return BLEST_ERR_DEVICE;
+  const uint32_t per_cu = std::min<uint32_t>((uint32_t)nb, g->opt.blocks_per_cu);
   g->grid = per_cu * (uint32_t)cus / g->nranges * g->nranges;
   if (g->grid == 0) return BLEST_ERR_DEVICE;
   int nbm = 0;
@@ -277,7 +303,9 @@ BfsParams base_params(const blest_graph* g) {
   p.vss_range = g->d_vss_range.as<uint8_t>();
   p.nranges = g->nranges;
   p.range_len = g->range_len;
-  p.range_words = g->range_words;
+  p.range_words = g->lazy ? g->range_words : 0;
+  p.lds_cshift = g->lds_cshift;
+  p.lds_min_len = std::min<uint32_t>(kLdsMinQueue, std::max<uint32_t>(1, p.range_words / 16));
   return p;
 }
 
@@ -298,6 +326,8 @@ void blest_default_options(blest_options* o) {
   o->blocks_per_cu = 1;
   o->group = 2;
   o->ranges = 0;
+  o->hubs = 0;
+  o->lds_kib = 0;
 }
 
 blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, const uint32_t* col_idx,
@@ -355,25 +385,43 @@ blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, cons
     rc = build_slices(work, o.sigma, o.slots, T, g->bvss);
     if (rc != kOk) return map_rc(rc);
     g->compression = g->bvss.num_slices ? (double)g->m / ((double)g->bvss.num_slices * o.sigma) : 0.0;
+    // the update-scheme policy reads the divergence of the ordering itself
     g->u_div_paper = update_divergence(g->bvss, 32, 32 / o.sigma);
     if (o.update == BLEST_UPDATE_AUTO)
       g->lazy = g->social && g->u_div_paper > 25000.0;
     else
       g->lazy = o.update == BLEST_UPDATE_LAZY;
-    // Row ranges: the lazy kernel keeps one range's visited bits per workgroup in
-    // LDS.  Auto picks the fewest ranges (a power of two) whose bitmap fits, and
-    // splits only when the lazy scheme is in use.
+    // Row ranges: with R > 1 every VSS is cut at range boundaries and workgroup b
+    // caches range b % R.  The cut multiplies the VSS count (3.6x at R-MAT scale 22
+    // with R = 8) and each frontier vertex is then marked by up to R workgroups,
+    // which costs more than the global visited checks it saves, so the default is
+    // one range, of which the LDS cache holds the first C words of every 64-word
+    // chunk (all of it when it fits).
     const uint32_t nw = (n + 31) / 32;
-    uint32_t R = o.ranges;
-    if (R == 0) {
-      R = 1;
-      if (g->lazy)
-        while (R < kMaxRanges && (uint64_t)((nw + R - 1) / R) * 4 > kMaxLdsRangeBytes) R *= 2;
-    }
+    const uint32_t R = o.ranges ? o.ranges : 1;
     const uint32_t rw = (nw + R - 1) / R;  // visited words per range
     g->nranges = R;
     g->range_len = rw * 32;
-    g->range_words = (uint64_t)rw * 4 <= kMaxLdsRangeBytes ? rw : 0;
+    g->lds_cap_words = o.lds_kib == BLEST_LDS_OFF ? 0u : (o.lds_kib ? o.lds_kib * 1024u : kMaxLdsBytes) / 4;
+    g->range_words = cache_shape(rw, g->lds_cap_words, g->lds_cshift);
+    g->order_id = g->new_id;
+    if (o.hubs == 2 || (o.hubs == 0 && g->social)) {
+      // Hub sort: the rows that most visited checks land on move into the cached
+      // positions (one range) or to the lowest IDs (several ranges).
+      g->hub_cpos = R == 1 && g->range_words ? 1u << g->lds_cshift : 0u;
+      std::vector<uint32_t> hub_id;
+      hub_sort(work, o.sigma, g->hub_cpos, hub_id);
+      Csr sorted;
+      relabel(work, hub_id, T, sorted);
+      work = std::move(sorted);
+      for (uint32_t v = 0; v < n; ++v) g->new_id[v] = hub_id[g->new_id[v]];
+      g->identity = false;
+      g->orig_id.assign(n, 0);
+      for (uint32_t v = 0; v < n; ++v) g->orig_id[g->new_id[v]] = v;
+      g->hubs_sorted = 1;
+      rc = build_slices(work, o.sigma, o.slots, T, g->bvss);
+      if (rc != kOk) return map_rc(rc);
+    }
     rc = partition_vss(g->bvss, R > 1 ? g->range_len : 0, T);
     if (rc != kOk) return map_rc(rc);
     if (g->bvss.num_vss >= (1u << (32 - kRangeBits))) return BLEST_ERR_TOO_LARGE;
@@ -631,6 +679,10 @@ blest_status blest_stats(blest_handle h, blest_stats_t* o) {
   o->bvss_bytes_table3 = b.num_slices * (4 + b.sigma / 8) + 4ull * (b.num_vss + b.num_sets);
   o->reorder_seconds = h->reorder_seconds;
   o->build_seconds = h->build_seconds;
+  o->hubs_sorted = h->hubs_sorted;
+  o->lds_bytes = h->lazy ? 4 * h->range_words : 0;
+  o->lds_chunk_words = h->lazy && h->range_words ? 1u << h->lds_cshift : 0;
+  o->hub_cpos = h->hub_cpos;
   return BLEST_OK;
 }
 
@@ -666,6 +718,7 @@ blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t cap
     case BLEST_EXPORT_ROW_IDS: src = b.row_ids.data(); bytes = 4ull * b.row_ids.size(); break;
     case BLEST_EXPORT_MASKS: src = b.masks.data(); bytes = b.masks.size(); break;
     case BLEST_EXPORT_VSS_RANGE: src = b.vss_range.data(); bytes = b.vss_range.size(); break;
+    case BLEST_EXPORT_ORDER_ID: src = h->order_id.data(); bytes = 4ull * h->order_id.size(); break;
     default: return BLEST_ERR_INVALID_ARGUMENT;
   }
   *size = bytes;

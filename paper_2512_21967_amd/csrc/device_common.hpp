@@ -79,53 +79,54 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Appends the VSS range of slice set ss at qn[pos ...].
-// `enc` maps a VSS ID to its queue entry.
-template <class Enc>
-__device__ __forceinline__ uint32_t push_set(const uint32_t* real_ptrs, uint32_t* qn, uint32_t pos, uint32_t ss,
-                                             Enc&& enc) {
-  const uint32_t b = real_ptrs[ss], e = real_ptrs[ss + 1];
-  for (uint32_t v = b; v < e; ++v) qn[pos++] = enc(v);
-  return pos;
-}
-
 struct PlainEntry {
   __device__ uint32_t operator()(uint32_t v) const { return v; }
 };
 
-// Writes the VSS ranges of the slice sets a lane owns: lanes with at most kSmallPush
-// VSSs write their own entries; larger ranges (hub slice sets can own thousands of
-// VSSs) are written by the whole wavefront, 64 entries per store instruction, so
-// one lane never serialises a long tail.  `sets(i)` gives the lane's i-th set for
-// i < nsets (uniform bound SETS); every lane of the wavefront must call this.
+// Writes a lane's VSS ranges [vb[i], vb[i] + vn[i]) for i < SETS (vn[i] = 0: none)
+// at qn[pos ...], in order; cnt is the sum of vn.  Lanes with at most kSmallPush
+// entries write their own; longer pushes (hub slice sets own thousands of VSSs)
+// are written by the whole wavefront, 4 x 64 entries per step, lane after lane.
+// The ranges arrive in registers, so the wavefront-wide part issues no load
+// besides what the encoder `enc` (VSS ID -> queue entry) reads.  Every lane of
+// the wavefront must call this.
 constexpr uint32_t kSmallPush = 8;
-template <int SETS, class SetOf, class Enc = PlainEntry>
-__device__ __forceinline__ void wave_push(const uint32_t* real_ptrs, uint32_t* qn, uint32_t pos, uint32_t cnt,
-                                          uint32_t setmask, SetOf&& set_of, Enc enc = Enc()) {
+template <int SETS, class Enc = PlainEntry>
+__device__ __forceinline__ void wave_push(uint32_t* qn, uint32_t pos, uint32_t cnt, const uint32_t (&vb)[SETS],
+                                          const uint32_t (&vn)[SETS], Enc enc = Enc()) {
   const bool small = cnt <= kSmallPush;
   if (small && cnt) {
 #pragma unroll
     for (int i = 0; i < SETS; ++i)
-      if (setmask & (1u << i)) pos = push_set(real_ptrs, qn, pos, set_of(i), enc);
+      for (uint32_t v = vb[i]; v < vb[i] + vn[i]; ++v) qn[pos++] = enc(v);
   }
   uint64_t big = __ballot(!small);
   while (big) {
     const uint32_t l = __ffsll((unsigned long long)big) - 1;
     big &= big - 1;
     uint32_t lp = readlane(pos, l);
-    const uint32_t lm = readlane(setmask, l);
 #pragma unroll
     for (int i = 0; i < SETS; ++i) {
-      if (lm & (1u << i)) {
-        const uint32_t ss = readlane(set_of(i), l);
-        const uint32_t b = real_ptrs[ss], e = real_ptrs[ss + 1];
-        for (uint32_t x = lane_id(); x < e - b; x += kWave) qn[lp + x] = enc(b + x);
-        lp += e - b;
+      const uint32_t n = readlane(vn[i], l);
+      if (n == 0) continue;
+      const uint32_t b = readlane(vb[i], l);
+      for (uint32_t x0 = 0; x0 < n; x0 += 4 * kWave) {
+        uint32_t val[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t x = x0 + j * kWave + lane_id();
+          val[j] = x < n ? enc(b + x) : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t x = x0 + j * kWave + lane_id();
+          if (x < n) qn[lp + x] = val[j];
+        }
       }
+      lp += n;
     }
   }
 }
-
 
 }  // namespace
 }  // namespace blest

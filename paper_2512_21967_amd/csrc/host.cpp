@@ -516,4 +516,52 @@ double update_divergence(const Bvss& b, uint32_t lanes, uint32_t slots_per_lane)
   return nvss ? sum / nvss : 0.0;
 }
 
+// Hub sort: sigma-aligned vertex groups (the future slice sets) are ranked by the
+// summed in-degree of their members, largest first, ties kept in order; members
+// keep their order inside a group.  Only groups inside complete 32-vertex words
+// move (the tail stays in place), so slice sets and masks are unchanged, and so is
+// the compression ratio.  Ranked groups fill words in rank order (32 / sigma
+// groups per word), and ranked words go first to the cached positions of the
+// lazy kernel's LDS cache - positions 0 .. cpos-1 of every 64-word chunk; the
+// t-th round over the chunks gives chunk c position (t + c) mod cpos - then to the
+// remaining positions in ascending order.  The hottest rows thus sit in the cache and are spread over all
+// chunks, so that no single wavefront of the frontier sweep owns all hub sets.
+void hub_sort(const Csr& g, uint32_t sigma, uint32_t cpos, std::vector<uint32_t>& new_id) {
+  const uint32_t n = g.n;
+  const uint32_t spw = 32 / sigma;          // groups per word
+  const uint32_t fw = n / 32;               // complete words
+  const uint64_t fg = (uint64_t)fw * spw;   // groups that move
+  std::vector<uint64_t> w(fg, 0);
+  for (uint64_t k = 0; k < g.nnz(); ++k) {
+    const uint32_t grp = g.col[k] / sigma;
+    if (grp < fg) w[grp] += 1;
+  }
+  std::vector<uint32_t> order(fg);
+  for (uint32_t x = 0; x < fg; ++x) order[x] = x;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return w[a] > w[b]; });
+  std::vector<uint32_t> slot;
+  slot.reserve(fw);
+  std::vector<uint8_t> taken(fw, 0);
+  const uint32_t chunks = (fw + 63) / 64;
+  const uint32_t cp = std::min<uint32_t>(cpos, 64);
+  for (uint32_t t = 0; t < cp; ++t)
+    for (uint32_t c = 0; c < chunks; ++c) {
+      // the position rotates with the chunk, so that equally hot words of
+      // different chunks fall into different LDS banks
+      const uint32_t q = c * 64 + (t + c) % cp;
+      if (q < fw) {
+        slot.push_back(q);
+        taken[q] = 1;
+      }
+    }
+  for (uint32_t q = 0; q < fw; ++q)
+    if (!taken[q]) slot.push_back(q);
+  new_id.resize(n);
+  for (uint64_t r = 0; r < fg; ++r) {
+    const uint64_t gnew = (uint64_t)slot[r / spw] * spw + r % spw;
+    for (uint32_t j = 0; j < sigma; ++j) new_id[(uint64_t)order[r] * sigma + j] = (uint32_t)(gnew * sigma + j);
+  }
+  for (uint64_t v = fg * sigma; v < n; ++v) new_id[v] = (uint32_t)v;
+}
+
 }  // namespace blest

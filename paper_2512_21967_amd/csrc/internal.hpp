@@ -41,6 +41,23 @@ void jaccard_windows(const Csr& g, const Csr& gt, uint32_t sigma, uint32_t w, in
 // Reverse Cuthill-McKee on the undirected view u.  Output: new_id.
 void rcm(const Csr& u, std::vector<uint32_t>& new_id);
 
+// Reorders sigma-aligned vertex groups by summed in-degree (largest first), keeping
+// each group intact, and places the hottest words at the first cpos positions of
+// every 64-word chunk (cpos = 0: plain rank order).  Output: new_id.
+void hub_sort(const Csr& g, uint32_t sigma, uint32_t cpos, std::vector<uint32_t>& new_id);
+
+// LDS cache of one row range of rw visited words: the first C = 2^cshift (<= 64)
+// words of every 64-word chunk, C as large as cap_words allows.  Returns the
+// cached word count (0 when not even one word per chunk fits).
+inline uint32_t cache_shape(uint32_t rw, uint32_t cap_words, uint32_t& cshift) {
+  const uint32_t chunks = (rw + 63) / 64;
+  cshift = 0;
+  if (chunks == 0 || cap_words < chunks) return 0;
+  const uint32_t per = cap_words / chunks;
+  while (cshift < 6 && (2u << cshift) <= per) ++cshift;
+  return chunks << cshift;
+}
+
 // The static BVSS arrays (Section 2.1) in this library's layout: the slices of a
 // slice set are sorted by row and cut into VSSs of at most tau = 64 * slots, a cut
 // also falling at every multiple of range_len in row ID (when range_len > 0) so

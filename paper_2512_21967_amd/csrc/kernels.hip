@@ -37,10 +37,17 @@ namespace blest {
 namespace {
 
 // Queue entry of VSS v: its ID and row range.
+// Queue entry of VSS v: (v << kRangeBits) | row range.  With one range the table
+// is not read (vss_range == nullptr), so pushes carry no load.
 struct RangeEntry {
   const uint8_t* vss_range;
-  __device__ uint32_t operator()(uint32_t v) const { return (v << kRangeBits) | vss_range[v]; }
+  __device__ uint32_t operator()(uint32_t v) const {
+    return vss_range ? (v << kRangeBits) | vss_range[v] : v << kRangeBits;
+  }
 };
+__device__ __forceinline__ RangeEntry range_entry(const BfsParams& p) {
+  return RangeEntry{p.nranges > 1 ? p.vss_range : nullptr};
+}
 
 __device__ __forceinline__ uint32_t to_orig(const BfsParams& p, uint32_t u) {
   return p.orig_id ? p.orig_id[u] : u;
@@ -162,23 +169,37 @@ __device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* 
   });
 }
 
-// Stage 1 of the lazy scheme with the visited bits in LDS.  Rows are split into
-// nranges ranges; workgroup b serves range b % nranges (with 8 ranges, one per XCD
-// under round-robin dispatch) and holds that range's current visited words in LDS,
-// reloaded at the start of every level.  Each wavefront of the range group looks at
-// 64 queue positions at a time, strided by the group's wavefront count so that
-// short queues still spread over the group, keeps the entries of its range, stages their
-// metadata in lanes and processes them G at a time.  A hit's check and its
-// de-duplication are LDS operations; only the first mark of a vertex within a
-// workgroup reaches global memory (a one-byte store into its reached byte).
+// Stage 1 of the lazy scheme with an LDS cache of visited bits.  Rows are split
+// into nranges ranges; workgroup b serves range b % nranges and, at the start of
+// every level with at least lds_min_len queue entries, copies into LDS the current
+// visited words 0 .. C-1 (C = 2^lds_cshift) of every 64-word chunk of its range:
+// word w of the range sits at LDS index (w / 64) * C + w % 64 when w % 64 < C.
+// With one range the hub sort puts the rows that draw most hits into exactly
+// those words.  Each wavefront of the range group looks at 64 queue positions at a time,
+// strided by the group's wavefront count so that short queues still spread over
+// the group, keeps the entries of its range, stages their metadata in lanes and
+// processes them G at a time.  A cached row's check and its de-duplication are LDS
+// operations (only the first mark of a vertex within a workgroup reaches global
+// memory); any other pulled row is marked without a check, since Stage 2 drops
+// reached rows that are already visited: a check in memory would make nearly
+// every group of slices wait for a load when hot and cold rows are interleaved.
+// A mark is a one-byte store into the row's reached byte.
 template <typename MT, int SLOTS, int G>
 __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32_t* qc, uint32_t len, uint32_t* lds) {
+  if (len < p.lds_min_len) {
+    stage1_lazy<MT, SLOTS, G>(p, qc, len);
+    return;
+  }
   constexpr int SIG = 8 * sizeof(MT);
   const uint32_t R = p.nranges;
   const uint32_t r = blockIdx.x % R;
-  const uint32_t w0 = r * (p.range_len >> 5);
-  for (uint32_t i = threadIdx.x; i < p.range_words; i += blockDim.x)
-    lds[i] = (w0 + i < p.n_words) ? p.vis[w0 + i] : 0u;
+  const uint32_t rw = p.range_len >> 5;  // words per range
+  const uint32_t w0 = r * rw;
+  const uint32_t cs = p.lds_cshift, cmask = (1u << cs) - 1u;
+  for (uint32_t i = threadIdx.x; i < p.range_words; i += blockDim.x) {
+    const uint32_t wr = ((i >> cs) << 6) | (i & cmask);
+    lds[i] = (wr < rw && w0 + wr < p.n_words) ? p.vis[w0 + wr] : 0u;
+  }
   __syncthreads();
   const uint32_t lane = lane_id();
   const uint32_t W = blockDim.x / kWave;
@@ -227,11 +248,18 @@ __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32
         for (int q = 0; q < SLOTS; ++q) {
           if ((uint32_t)g.m[k][q] & g.alpha[k]) {
             const uint32_t u = g.u[k][q];
-            const uint32_t ul = u - rbase;
+            const uint32_t wr = (u - rbase) >> 5;
             const uint32_t bit = 1u << (u & 31);
-            if (!(lds[ul >> 5] & bit)) {
-              const uint32_t old = atomicOr(&lds[ul >> 5], bit);
-              if (!(old & bit)) p.mark[u] = 1;
+            if ((wr & 63u) <= cmask) {
+              const uint32_t li = ((wr >> 6) << cs) | (wr & 63u);
+              if (!(lds[li] & bit)) {
+                const uint32_t old = atomicOr(&lds[li], bit);
+                if (!(old & bit)) p.mark[u] = 1;
+              }
+            } else {
+              // uncached row: marked without a visited check (Stage 2 keeps
+              // only reached rows that are not yet visited), so no load waits
+              p.mark[u] = 1;
             }
           }
         }
@@ -250,9 +278,14 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, ui
   __shared__ uint32_t s_base;
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
-  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < p.n_words; b0 += gridDim.x * blockDim.x) {
-    const uint32_t t = b0 + threadIdx.x;
-    uint32_t cnt = 0, pushmask = 0;
+  // Wavefront-sized chunks of 64 words are dealt round-robin over the workgroups,
+  // so that the low IDs, where the hub sort puts the sets with the most VSSs,
+  // spread over many workgroups instead of loading the first few.
+  for (uint32_t b0 = 0; b0 < p.n_words; b0 += gridDim.x * blockDim.x) {
+    const uint32_t t = b0 + (wave * gridDim.x + blockIdx.x) * kWave + lane;
+    uint32_t cnt = 0, vb[SPW], vn[SPW];
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) vb[i] = vn[i] = 0;
     if (t < p.n_words) {
       // the 32 reached bytes of word t, folded into one bit each
       const uint4* mb = reinterpret_cast<const uint4*>(p.mark + 32ull * t);
@@ -270,18 +303,32 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, ui
       if (diff) {
         p.vis[t] = cur | diff;
         p.front[t] = diff;
-        uint32_t d = diff;
-        while (d) {
-          const uint32_t b = __ffs(d) - 1;
-          p.levels[to_orig(p, t * 32 + b)] = level;
-          d &= d - 1;
+        // levels of the new vertices: their original IDs are loaded 8 at a time
+        // (two 16-byte loads) so that the stores do not wait one by one
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const uint32_t d8 = (diff >> (8 * c)) & 0xFFu;
+          if (!d8) continue;
+          uint32_t o[8];
+          if (p.orig_id) {
+            const uint4* op = reinterpret_cast<const uint4*>(p.orig_id + 32ull * t + 8 * c);
+            const uint4 a = op[0], b = op[1];
+            o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w; o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+          } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) o[j] = t * 32 + 8 * c + j;
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (d8 & (1u << j)) p.levels[o[j]] = level;
         }
 #pragma unroll
         for (int i = 0; i < SPW; ++i) {
           if ((diff >> (i * SIG)) & chunk_mask<SIG>()) {
             const uint32_t ss = t * SPW + i;
-            pushmask |= 1u << i;
-            cnt += p.real_ptrs[ss + 1] - p.real_ptrs[ss];
+            vb[i] = p.real_ptrs[ss];
+            vn[i] = p.real_ptrs[ss + 1] - vb[i];
+            cnt += vn[i];
           }
         }
       }
@@ -300,7 +347,7 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, ui
     }
     __syncthreads();
     const uint32_t pos = s_base + s_wave[wave] + incl - cnt;
-    wave_push<SPW>(p.real_ptrs, qn, pos, cnt, pushmask, [&](int i) { return t * SPW + i; }, RangeEntry{p.vss_range});
+    wave_push<SPW>(qn, pos, cnt, vb, vn, range_entry(p));
     __syncthreads();
   }
 }
@@ -323,7 +370,9 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
         const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
         vw[k][r] = p.vis[hit ? (g.u[k][r] >> 5) : 0u];
       }
-    uint32_t pushmask = 0, cnt = 0;
+    uint32_t cnt = 0, vb[G * SLOTS], vn[G * SLOTS];
+#pragma unroll
+    for (int i = 0; i < G * SLOTS; ++i) vb[i] = vn[i] = 0;
 #pragma unroll
     for (int k = 0; k < G; ++k)
 #pragma unroll
@@ -339,8 +388,9 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
             const uint32_t sh = (x & 31) & ~(uint32_t)(SIG - 1);
             if (((old >> sh) & chunk_mask<SIG>()) == 0) {
               const uint32_t ss = x / SIG;
-              pushmask |= 1u << (k * SLOTS + r);
-              cnt += p.real_ptrs[ss + 1] - p.real_ptrs[ss];
+              vb[k * SLOTS + r] = p.real_ptrs[ss];
+              vn[k * SLOTS + r] = p.real_ptrs[ss + 1] - vb[k * SLOTS + r];
+              cnt += vn[k * SLOTS + r];
             }
           }
         }
@@ -348,8 +398,7 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
     uint32_t total;
     const uint32_t pos = wave_reserve(qlen, cnt, total);
     if (total != 0)
-      wave_push<G * SLOTS>(p.real_ptrs, qn, pos, cnt, pushmask, [&](int i) { return g.u[i / SLOTS][i % SLOTS] / SIG; },
-                           RangeEntry{p.vss_range});
+      wave_push<G * SLOTS>(qn, pos, cnt, vb, vn, range_entry(p));
   });
 }
 
@@ -402,7 +451,7 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
       p.front[2 * p.n_words + t] = 0;
     }
   }
-  for (uint32_t j = tid; j < q0n; j += nt) p.queue[j] = RangeEntry{p.vss_range}(q0b + j);
+  for (uint32_t j = tid; j < q0n; j += nt) p.queue[j] = range_entry(p)(q0b + j);
   if (tid == 0) {
     qlen[0] = q0n;
     qlen[kLine] = 0;

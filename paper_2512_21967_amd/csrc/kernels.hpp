@@ -23,7 +23,7 @@ struct BfsParams {
   const uint32_t* vss_beg;
   const uint32_t* v2r;
   const uint32_t* real_ptrs;
-  const uint32_t* orig_id;  // new label -> original ID; nullptr = identity
+  const uint32_t* orig_id;  // new label -> original ID, 32 * n_words entries; nullptr = identity
   const uint8_t* vss_range; // row range of each VSS
   // per-call workspace
   uint32_t* vis;            // visited bits, n_words
@@ -36,19 +36,23 @@ struct BfsParams {
   uint32_t src;             // source, new label
   uint32_t nranges;         // row ranges (a power of two, at most kMaxRanges)
   uint32_t range_len;       // rows per range (a multiple of 32)
-  uint32_t range_words;     // visited words of one range held in LDS (0: none)
+  uint32_t range_words;     // visited words of a range cached in LDS (0: none)
+  uint32_t lds_cshift;      // the cache holds words 0 .. 2^lds_cshift - 1 of every 64-word chunk
+  uint32_t lds_min_len;     // lazy: levels with fewer queue entries skip the LDS cache
 };
 
 // Queue entries carry the VSS's row range in their low bits.
 constexpr uint32_t kRangeBits = 5;
 constexpr uint32_t kMaxRanges = 1u << kRangeBits;
-constexpr uint32_t kMaxLdsRangeBytes = 64 * 1024;
+constexpr uint32_t kMaxLdsBytes = 128 * 1024;
 
 // Persistent single-source BFS; lazy selects Algorithm 3, otherwise Algorithm 2.
 // grid must be co-resident (the call uses a cooperative launch) and a multiple of
 // p.nranges.  group = VSSs whose slice loads a wavefront keeps in flight together
-// (1, 2, 4).  With p.range_words > 0 the lazy kernel keeps the visited bits of
-// each workgroup's row range in LDS (4 * range_words bytes of dynamic LDS).
+// (1, 2, 4).  With p.range_words > 0 the lazy kernel caches, per workgroup, the
+// visited words 0 .. 2^lds_cshift - 1 of every 64-word chunk of the workgroup's
+// row range in LDS (4 * range_words bytes of dynamic LDS); other rows are checked
+// in memory.
 hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, uint32_t grid,
                       uint32_t block, hipStream_t stream);
 

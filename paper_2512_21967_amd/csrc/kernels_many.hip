@@ -89,7 +89,9 @@ __global__ __launch_bounds__(kManyBlock) void bfs_many_kernel(const ManyItem* __
     // ---- Stage 2: sweep the LDS bitmaps ----
     for (uint32_t b0 = 0; b0 < nw; b0 += blockDim.x) {
       const uint32_t t = b0 + threadIdx.x;
-      uint32_t cnt = 0, pushmask = 0;
+      uint32_t cnt = 0, vb[SPW], vn[SPW];
+#pragma unroll
+      for (int i = 0; i < SPW; ++i) vb[i] = vn[i] = 0;
       if (t < nw) {
         const uint32_t cur = vis[2 * t], nxt = vis[2 * t + 1];
         const uint32_t diff = cur ^ nxt;
@@ -106,8 +108,9 @@ __global__ __launch_bounds__(kManyBlock) void bfs_many_kernel(const ManyItem* __
           for (int i = 0; i < SPW; ++i) {
             if ((diff >> (i * SIG)) & (SIG == 32 ? 0xFFFFFFFFu : ((1u << SIG) - 1u))) {
               const uint32_t s = t * SPW + i;
-              pushmask |= 1u << i;
-              cnt += it.real_ptrs[s + 1] - it.real_ptrs[s];
+              vb[i] = it.real_ptrs[s];
+              vn[i] = it.real_ptrs[s + 1] - vb[i];
+              cnt += vn[i];
             }
           }
         }
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(kManyBlock) void bfs_many_kernel(const ManyItem* __
       }
       __syncthreads();
       const uint32_t pos = s_base + s_wave[wave] + incl - cnt;
-      wave_push<SPW>(it.real_ptrs, qn, pos, cnt, pushmask, [&](int i) { return t * SPW + i; });
+      wave_push<SPW>(qn, pos, cnt, vb, vn);
       __syncthreads();
     }
     // queue entries written by other waves must be visible before Stage 1 reads them

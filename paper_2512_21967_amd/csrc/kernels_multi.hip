@@ -104,11 +104,12 @@ __device__ __forceinline__ void multi_stage2(const MultiParams& p, uint32_t* qn,
     }
     // a slice set is active iff one of its sigma consecutive vertices changed
     const uint64_t changed = __ballot(diff != 0);
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, vb[1] = {0}, vn[1] = {0};
     const bool leader = (lane % SIG) == 0 && u < p.n;
     if (leader && ((changed >> lane) & (SIG == 64 ? ~0ull : ((1ull << SIG) - 1))) != 0) {
       const uint32_t ss = u / SIG;
-      cnt = p.real_ptrs[ss + 1] - p.real_ptrs[ss];
+      vb[0] = p.real_ptrs[ss];
+      vn[0] = cnt = p.real_ptrs[ss + 1] - vb[0];
     }
     const uint32_t incl = wave_inclusive_scan(cnt);
     if (lane == kWave - 1) s_wave[wave] = incl;
@@ -124,7 +125,7 @@ __device__ __forceinline__ void multi_stage2(const MultiParams& p, uint32_t* qn,
     }
     __syncthreads();
     const uint32_t pos = s_base + s_wave[wave] + incl - cnt;
-    wave_push<1>(p.real_ptrs, qn, pos, cnt, cnt ? 1u : 0u, [&](int) { return u / SIG; });
+    wave_push<1>(qn, pos, cnt, vb, vn);
     __syncthreads();
   }
 }

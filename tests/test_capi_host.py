@@ -148,7 +148,10 @@ def check_bvss_against_oracle(gr, g, sigma, slots):
     np.testing.assert_array_equal(g.export("vss_range"), part["blocks"])
     assert st["num_slices"] == len(sid) and st["num_vss"] == len(v2r) and st["tau"] == tau
     assert st["compression"] == pytest.approx(obvss.compression_ratio(h.nnz, len(sid), sigma))
-    paper_groups = obvss.vss_partition(sid, row, mask, n_sets, 32 * (32 // sigma))["groups"]
+    # the update-scheme policy reads the divergence of the ordering before the hub sort
+    o = relabelled(gr, g.export("order_id"))
+    osid, orow, omask = obvss.slices(o, sigma)
+    paper_groups = obvss.vss_partition(osid, orow, omask, n_sets, 32 * (32 // sigma))["groups"]
     assert st["u_div_paper"] == pytest.approx(obvss.update_divergence(paper_groups, 32), rel=1e-9, abs=1e-9)
     assert st["u_div_native"] == pytest.approx(obvss.update_divergence(part["groups"], 64), rel=1e-9, abs=1e-9)
     assert st["nranges"] >= 1 and st["range_len"] % 32 == 0
@@ -184,12 +187,12 @@ def test_bvss_row_ranges_match_oracle(ranges):
         assert np.all(rows[beg[v]:beg[v + 1]] // st["range_len"] == rng[v])
 
 
-def test_auto_ranges_follow_the_update_scheme():
+def test_auto_ranges_keep_one_range():
     gr = inputs.rmat_workload(20, 8, seed=1, permute_seed=2)
     lazy = host_graph(gr, reorder="none", update="lazy").stats()
     eager = host_graph(gr, reorder="none", update="eager").stats()
-    # 2^20 vertices = 128 KB of visited bits: two 64 KB ranges for the lazy kernel
-    assert lazy["nranges"] == 2 and eager["nranges"] == 1
+    assert lazy["nranges"] == 1 and eager["nranges"] == 1
+    assert lazy["range_len"] >= gr.n and lazy["num_vss"] == eager["num_vss"]
 
 
 @pytest.mark.parametrize("reorder", ["compression", "bandwidth"])
@@ -216,7 +219,9 @@ def test_jaccard_windows_matches_oracle(seed):
         m = n * int(rng.integers(1, 6))
         gr = inputs.from_arcs(n, rng.integers(0, n, m), rng.integers(0, n, m), bool(seed % 3))
     g = host_graph(gr, sigma=sigma, window=w, reorder="compression")
-    np.testing.assert_array_equal(g.export("new_id"), oreorder.jaccard_with_windows(gr, sigma, w))
+    np.testing.assert_array_equal(g.export("order_id"), oreorder.jaccard_with_windows(gr, sigma, w))
+    if not g.stats()["hubs_sorted"]:
+        np.testing.assert_array_equal(g.export("new_id"), g.export("order_id"))
 
 
 def test_jaccard_windows_matches_oracle_hand_cases():
@@ -225,7 +230,7 @@ def test_jaccard_windows_matches_oracle_hand_cases():
         src = [u for u, vs in adj.items() for _ in vs]
         dst = [v for vs in adj.values() for v in vs]
         gr = inputs.from_arcs(n, src, dst, False)
-        g = host_graph(gr, sigma=sigma, window=w, reorder="compression")
+        g = host_graph(gr, sigma=sigma, window=w, reorder="compression", hubs="off")
         np.testing.assert_array_equal(g.export("new_id"), oreorder.jaccard_with_windows(gr, sigma, w))
 
 
@@ -243,7 +248,67 @@ def test_rcm_matches_oracle(case):
     else:
         gr = inputs.from_arcs(30, [1, 5, 9], [2, 6, 10], True)
     g = host_graph(gr, reorder="bandwidth")
-    np.testing.assert_array_equal(g.export("new_id"), oreorder.rcm(gr))
+    np.testing.assert_array_equal(g.export("order_id"), oreorder.rcm(gr))
+
+
+def hub_sorted_labels(gr, order_id, sigma, cpos):
+    """The hub sort by its definition: the sigma-groups inside complete 32-vertex
+    words, ranked by summed in-degree (largest first, ties in order), fill words in
+    rank order; ranked words take the positions 0..cpos-1 of every 64-word chunk
+    first (round t gives chunk c position (t + c) mod cpos), then the other
+    positions in order."""
+    spw = 32 // sigma
+    fw = gr.n // 32
+    fg = fw * spw
+    indeg = np.bincount(gr.col.astype(np.int64), minlength=gr.n)
+    lab_deg = np.zeros(gr.n, np.int64)
+    lab_deg[order_id] = indeg
+    w = lab_deg[:fg * sigma].reshape(fg, sigma).sum(axis=1) if fg else np.zeros(0, np.int64)
+    ranked = sorted(range(fg), key=lambda g: (-w[g], g))
+    chunks = -(-fw // 64)
+    cp = min(cpos, 64)
+    slots = [c * 64 + (t + c) % cp for t in range(cp) for c in range(chunks) if c * 64 + (t + c) % cp < fw]
+    first = set(slots)
+    slots += [q for q in range(fw) if q not in first]
+    new_group = np.empty(fg, np.int64)
+    for r, g in enumerate(ranked):
+        new_group[g] = slots[r // spw] * spw + r % spw
+    out = order_id.astype(np.int64).copy()
+    move = out < fg * sigma
+    out[move] = new_group[out[move] // sigma] * sigma + out[move] % sigma
+    return out
+
+
+@pytest.mark.parametrize("case", ["rmat-compression", "rmat-none", "ragged", "directed", "small-cache", "no-cache"])
+def test_hub_sort_follows_its_definition(case):
+    rng = np.random.default_rng(4)
+    if case == "rmat-compression":
+        gr, kw = inputs.rmat_workload(10, 8, seed=5, permute_seed=1), dict(reorder="compression", window=256)
+    elif case == "rmat-none":
+        gr, kw = inputs.rmat_workload(10, 16, seed=2), dict(reorder="none", sigma=16)
+    elif case == "ragged":  # n not a multiple of sigma: the partial group stays last
+        src = (rng.pareto(1.5, 6000) * 10).astype(np.int64) % 1001
+        gr, kw = inputs.from_arcs(1001, src, rng.integers(0, 1001, 6000), True), dict(reorder="none")
+    elif case == "directed":
+        gr, kw = inputs.from_arcs(300, rng.integers(0, 300, 2000) ** 2 % 300, rng.integers(0, 300, 2000), False), \
+            dict(reorder="none")
+    elif case == "small-cache":  # 512 words in 8 chunks, 256 cached words: the first 32 of each chunk
+        gr, kw = inputs.rmat_workload(14, 8, seed=9, permute_seed=3), dict(reorder="none", lds_kib=1)
+    else:
+        gr, kw = inputs.rmat_workload(14, 8, seed=9, permute_seed=3), dict(reorder="none", lds_kib=None)
+    sigma = kw.get("sigma", 8)
+    off = host_graph(gr, hubs="off", **kw)
+    on = host_graph(gr, hubs="on", **kw)
+    assert on.stats()["hubs_sorted"] == 1 and off.stats()["hubs_sorted"] == 0
+    np.testing.assert_array_equal(on.export("order_id"), off.export("new_id"))
+    cpos = on.stats()["hub_cpos"]
+    assert cpos == {"small-cache": 32, "no-cache": 0}.get(case, 64)
+    np.testing.assert_array_equal(on.export("new_id"), hub_sorted_labels(gr, on.export("order_id"), sigma, cpos))
+    # same slice sets and masks, so the same slice count and compression
+    a, b = on.stats(), off.stats()
+    assert a["num_slices"] == b["num_slices"] and a["compression"] == b["compression"]
+    assert a["u_div_paper"] == pytest.approx(b["u_div_paper"], rel=1e-12)
+    check_bvss_against_oracle(gr, on, sigma, 4)
 
 
 def test_social_like_and_auto_policy():

@@ -161,14 +161,30 @@ def test_row_ranges(ranges, update):
     check_sources(gr, g, inputs.sources(gr, seed=ranges, k=3))
 
 
-def test_lazy_without_lds_bitmap():
-    """A graph whose visited bitmap does not fit one LDS range, forced to one range:
-    the lazy kernel checks visited bits in global memory."""
+def test_lazy_with_partial_lds_cache():
+    """A graph whose visited bitmap is larger than the LDS cache: the lowest rows
+    are checked in LDS, the others in global memory (S20, 64 KiB cache)."""
     gr = inputs.rmat_workload(20, 4, seed=2, permute_seed=1)
-    g = blest.Graph(gr, update="lazy", reorder="none", ranges=1)
+    g = blest.Graph(gr, update="lazy", reorder="none", ranges=1, lds_kib=64)
+    st = g.stats()
+    assert st["hubs_sorted"] == 1 and st["lds_bytes"] * 8 == gr.n // 2
     check_sources(gr, g, inputs.sources(gr, seed=1, k=2))
     g.configure(update="eager")
     check_sources(gr, g, inputs.sources(gr, seed=2, k=1))
+
+
+@pytest.mark.parametrize("lds_kib", [1, 4, None])
+@pytest.mark.parametrize("ranges", [1, 4])
+@pytest.mark.parametrize("hubs", ["on", "off"])
+def test_lds_cache_sizes(lds_kib, ranges, hubs):
+    """Small LDS caches (1 KiB = 8192 rows, 4 KiB) so that most levels use the cache
+    and many rows fall outside it; None = no cache (global checks only)."""
+    gr = inputs.rmat_workload(15, 16, seed=7, permute_seed=8)
+    g = blest.Graph(gr, update="lazy", reorder="none", ranges=ranges, hubs=hubs, lds_kib=lds_kib)
+    st = g.stats()
+    assert st["lds_bytes"] == (0 if lds_kib is None else min(lds_kib * 1024, st["range_len"] // 8))
+    assert st["hubs_sorted"] == (hubs == "on")
+    check_sources(gr, g, inputs.sources(gr, seed=ranges, k=3))
 
 
 def test_full_size_s22_config_sampled_sources():
@@ -177,5 +193,6 @@ def test_full_size_s22_config_sampled_sources():
     gr = inputs.rmat_workload(22, 16, seed=1, permute_seed=2)
     g = blest.Graph(gr, reorder="compression")
     st = g.stats()
-    assert st["update_used"] == "lazy" and st["nranges"] == 8
+    assert st["update_used"] == "lazy" and st["nranges"] == 1 and st["hubs_sorted"] == 1
+    assert st["lds_bytes"] == 128 * 1024 and st["lds_bytes"] * 8 < gr.n
     check_sources(gr, g, inputs.sources(gr, seed=3, k=64)[:2])
