@@ -232,7 +232,7 @@ SingleWorkspace* single_workspace(blest_graph* g, void* stream, blest_status* st
   auto ws = std::make_unique<SingleWorkspace>();
   const size_t nw = g->n_words();
   hipError_t e = ws->vis.alloc(sizeof(uint32_t) * nw);
-  if (e == hipSuccess) e = ws->mark.alloc(32 * nw);
+  if (e == hipSuccess) e = ws->mark.alloc(32 * nw + 64);  // + one never-read byte per lane
   if (e == hipSuccess) e = ws->front.alloc(sizeof(uint32_t) * 3 * nw);
   if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 3 * std::max<size_t>(g->bvss.num_vss, 1));
   if (e == hipSuccess) e = ws->ctrl.alloc(sizeof(uint32_t) * kCtrlWords);

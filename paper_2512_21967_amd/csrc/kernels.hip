@@ -86,26 +86,47 @@ struct VssGroup {
 };
 
 
+// Loads slot r of a VSS whose slices are [beg, end) for every lane.  The loads
+// are issued unconditionally (lanes past the end re-read slice beg, a line the
+// wavefront fetches anyway, and then drop it): with no branch around them the
+// compiler knows how many memory operations follow each load and can wait for
+// exactly the ones it needs instead of draining everything.
+template <typename MT, int SLOTS, int G>
+__device__ __forceinline__ void load_vss(const BfsParams& p, uint32_t beg, uint32_t end, int k,
+                                         VssGroup<MT, SLOTS, G>& g) {
+  const MT* masks = static_cast<const MT*>(p.masks);
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int r = 0; r < SLOTS; ++r) {
+    const uint32_t idx = beg + lane + r * kWave;
+    const bool ok = idx < end;
+    const uint32_t at = ok ? idx : beg;
+    const MT mv = masks[at];
+    const uint32_t uv = p.row_ids[at];
+    g.m[k][r] = ok ? mv : MT(0);
+    g.u[k][r] = ok ? uv : 0u;
+  }
+}
+
 // Issues the mask and row-ID loads of the VSSs whose metadata sits in lanes
 // k0 .. k0 + G - 1 of (mb, me, ma); lanes >= cnt are empty.
 template <typename MT, int SLOTS, int G>
 __device__ __forceinline__ void load_group(const BfsParams& p, uint32_t mb, uint32_t me, uint32_t ma, uint32_t k0,
                                            uint32_t cnt, VssGroup<MT, SLOTS, G>& g) {
-  const MT* masks = static_cast<const MT*>(p.masks);
-  const uint32_t lane = lane_id();
 #pragma unroll
   for (int k = 0; k < G; ++k) {
     const uint32_t src = k0 + k < cnt ? k0 + k : 63u;  // lane 63 holds an empty VSS when cnt < 64
     const uint32_t beg = readlane(mb, src), end = k0 + k < cnt ? readlane(me, src) : beg;
     g.alpha[k] = readlane(ma, src);
-#pragma unroll
-    for (int r = 0; r < SLOTS; ++r) {
-      const uint32_t idx = beg + lane + r * kWave;
-      const bool ok = idx < end;
-      g.m[k][r] = ok ? masks[idx] : MT(0);
-      g.u[k][r] = ok ? p.row_ids[idx] : 0u;
-    }
+    load_vss<MT, SLOTS, G>(p, beg, end, k, g);
   }
+}
+
+// Address of a reached byte to store 1 into: the row's own, or this lane's byte
+// in the padding past the array (never read) when no mark is due, so that the
+// store can be issued unconditionally.
+__device__ __forceinline__ uint8_t* mark_slot(const BfsParams& p, bool need, uint32_t u) {
+  return need ? p.mark + u : p.mark + 32ull * p.n_words + lane_id();
 }
 
 // Stage 1 driver shared by both schemes.  Wavefront w processes the queue
@@ -114,11 +135,13 @@ __device__ __forceinline__ void load_group(const BfsParams& p, uint32_t mb, uint
 // l-th next position - VSS slice range and the sigma-bit frontier chunk alpha of
 // its slice set - so the dependent queue -> metadata -> frontier loads are paid
 // once per 64 VSSs; the values are then broadcast with readlane.  VSSs are taken
-// G at a time, and the next group's slice loads are issued before the current
-// group is applied.
-template <typename MT, int SLOTS, int G, class Apply>
+// G at a time in three steps: issue(cur) starts the group's own loads (visited
+// words), the next group's slice loads follow, then finish(cur, issued) uses the
+// results; every step is free of branches around memory operations, so each wait
+// covers only the loads it needs.
+template <typename MT, int SLOTS, int G, class Issue, class Finish>
 __device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, uint32_t len, const uint32_t* fcur,
-                                       Apply&& apply) {
+                                       Issue&& issue, Finish&& finish) {
   constexpr int SIG = 8 * sizeof(MT);
   const uint32_t lane = lane_id();
   const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -136,8 +159,9 @@ __device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, u
     VssGroup<MT, SLOTS, G> cur, nxt;
     load_group<MT, SLOTS, G>(p, mb, me, ma, 0, cnt, cur);
     for (uint32_t k = 0; k < cnt; k += G) {
-      if (k + G < cnt) load_group<MT, SLOTS, G>(p, mb, me, ma, k + G, cnt, nxt);
-      apply(cur);
+      const auto issued = issue(cur);
+      load_group<MT, SLOTS, G>(p, mb, me, ma, k + G, cnt, nxt);  // empty past the end
+      finish(cur, issued);
       cur = nxt;
     }
   }
@@ -150,23 +174,30 @@ __device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, u
 // needed (device-scope atomic ORs cost an order of magnitude more on MI355X).
 template <typename MT, int SLOTS, int G>
 __device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* qc, uint32_t len) {
-  stage1<MT, SLOTS, G>(p, qc, len, p.front, [&](const VssGroup<MT, SLOTS, G>& g) {
-    uint32_t cw[G][SLOTS];
+  using Words = struct { uint32_t w[G][SLOTS]; };
+  stage1<MT, SLOTS, G>(
+      p, qc, len, p.front,
+      [&](const VssGroup<MT, SLOTS, G>& g) {
+        Words cw;
 #pragma unroll
-    for (int k = 0; k < G; ++k)
+        for (int k = 0; k < G; ++k)
 #pragma unroll
-      for (int r = 0; r < SLOTS; ++r) {
-        const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
-        cw[k][r] = p.vis[hit ? (g.u[k][r] >> 5) : 0u];
-      }
+          for (int r = 0; r < SLOTS; ++r) {
+            const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
+            cw.w[k][r] = p.vis[hit ? (g.u[k][r] >> 5) : 0u];
+          }
+        return cw;
+      },
+      [&](const VssGroup<MT, SLOTS, G>& g, const Words& cw) {
 #pragma unroll
-    for (int k = 0; k < G; ++k)
+        for (int k = 0; k < G; ++k)
 #pragma unroll
-      for (int r = 0; r < SLOTS; ++r) {
-        const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
-        if (hit && !(cw[k][r] & (1u << (g.u[k][r] & 31)))) p.mark[g.u[k][r]] = 1;
-      }
-  });
+          for (int r = 0; r < SLOTS; ++r) {
+            const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
+            const bool need = hit && !(cw.w[k][r] & (1u << (g.u[k][r] & 31)));
+            *mark_slot(p, need, g.u[k][r]) = 1;
+          }
+      });
 }
 
 // Stage 1 of the lazy scheme with an LDS cache of visited bits.  Rows are split
@@ -218,51 +249,57 @@ __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32
       me = p.vss_beg[v + 1];
       ma = frontier_chunk<SIG>(p.front, p.v2r[v]);
     }
-    while (pick) {
-      // the next G picked lanes (uniform); missing ones read an empty VSS
-      uint32_t src[G];
+    // G picked lanes at a time (uniform); missing ones read an empty VSS.  The
+    // next group's slice loads are issued before the current group is applied.
+    auto take = [&](uint32_t (&src)[G], VssGroup<MT, SLOTS, G>& g) {
 #pragma unroll
       for (int k = 0; k < G; ++k) {
         src[k] = pick ? (uint32_t)(__ffsll((unsigned long long)pick) - 1) : 64u;
         pick &= pick - 1;
-      }
-      VssGroup<MT, SLOTS, G> g;
-      const MT* masks = static_cast<const MT*>(p.masks);
-#pragma unroll
-      for (int k = 0; k < G; ++k) {
         const bool ok_k = src[k] < 64u;
-        const uint32_t beg = ok_k ? readlane(mb, src[k]) : 0u;
-        const uint32_t end = ok_k ? readlane(me, src[k]) : 0u;
-        g.alpha[k] = ok_k ? readlane(ma, src[k]) : 0u;
-#pragma unroll
-        for (int q = 0; q < SLOTS; ++q) {
-          const uint32_t idx = beg + lane + q * kWave;
-          const bool ok = idx < end;
-          g.m[k][q] = ok ? masks[idx] : MT(0);
-          g.u[k][q] = ok ? p.row_ids[idx] : 0u;
-        }
+        const uint32_t beg = ok_k ? readlane(mb, src[k] & 63u) : 0u;
+        const uint32_t end = ok_k ? readlane(me, src[k] & 63u) : 0u;
+        g.alpha[k] = ok_k ? readlane(ma, src[k] & 63u) : 0u;
+        load_vss<MT, SLOTS, G>(p, beg, end, k, g);
       }
+    };
+    uint32_t src[G];
+    VssGroup<MT, SLOTS, G> cur, nxt;
+    take(src, cur);
+    while (src[0] < 64u) {
+      take(src, nxt);
+      // cached hits: all LDS words first, then de-duplicating ORs where unvisited
+      uint32_t lw[G][SLOTS];
+      bool need[G][SLOTS];
 #pragma unroll
       for (int k = 0; k < G; ++k)
 #pragma unroll
         for (int q = 0; q < SLOTS; ++q) {
-          if ((uint32_t)g.m[k][q] & g.alpha[k]) {
-            const uint32_t u = g.u[k][q];
-            const uint32_t wr = (u - rbase) >> 5;
-            const uint32_t bit = 1u << (u & 31);
-            if ((wr & 63u) <= cmask) {
-              const uint32_t li = ((wr >> 6) << cs) | (wr & 63u);
-              if (!(lds[li] & bit)) {
-                const uint32_t old = atomicOr(&lds[li], bit);
-                if (!(old & bit)) p.mark[u] = 1;
-              }
-            } else {
-              // uncached row: marked without a visited check (Stage 2 keeps
-              // only reached rows that are not yet visited), so no load waits
-              p.mark[u] = 1;
-            }
+          const uint32_t wr = (cur.u[k][q] - rbase) >> 5;
+          const bool hit = ((uint32_t)cur.m[k][q] & cur.alpha[k]) != 0;
+          const bool in = hit && (wr & 63u) <= cmask;
+          lw[k][q] = lds[in ? (((wr >> 6) << cs) | (wr & 63u)) : 0u];
+          // an uncached row is marked without a visited check: Stage 2 keeps only
+          // reached rows that are not yet visited, and a check in memory would
+          // make nearly every group wait for a load
+          need[k][q] = hit && (!in || !(lw[k][q] & (1u << (cur.u[k][q] & 31))));
+        }
+#pragma unroll
+      for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+          const uint32_t wr = (cur.u[k][q] - rbase) >> 5;
+          if (need[k][q] && (wr & 63u) <= cmask) {
+            const uint32_t bit = 1u << (cur.u[k][q] & 31);
+            const uint32_t old = atomicOr(&lds[((wr >> 6) << cs) | (wr & 63u)], bit);
+            need[k][q] = !(old & bit);
           }
         }
+#pragma unroll
+      for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) *mark_slot(p, need[k][q], cur.u[k][q]) = 1;
+      cur = nxt;
     }
   }
 }
@@ -361,15 +398,20 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
                                              const uint32_t* fc, uint32_t* fn, uint32_t* qn, uint32_t* qlen,
                                              int32_t level) {
   constexpr int SIG = 8 * sizeof(MT);
-  stage1<MT, SLOTS, G>(p, qc, len, fc, [&](const VssGroup<MT, SLOTS, G>& g) {
-    uint32_t vw[G][SLOTS];
+  using Words = struct { uint32_t w[G][SLOTS]; };
+  auto issue = [&](const VssGroup<MT, SLOTS, G>& g) {
+    Words vw;
 #pragma unroll
     for (int k = 0; k < G; ++k)
 #pragma unroll
       for (int r = 0; r < SLOTS; ++r) {
         const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
-        vw[k][r] = p.vis[hit ? (g.u[k][r] >> 5) : 0u];
+        vw.w[k][r] = p.vis[hit ? (g.u[k][r] >> 5) : 0u];
       }
+    return vw;
+  };
+  stage1<MT, SLOTS, G>(p, qc, len, fc, issue, [&](const VssGroup<MT, SLOTS, G>& g, const Words& vw_) {
+    const auto& vw = vw_.w;
     uint32_t cnt = 0, vb[G * SLOTS], vn[G * SLOTS];
 #pragma unroll
     for (int i = 0; i < G * SLOTS; ++i) vb[i] = vn[i] = 0;

@@ -27,7 +27,7 @@ struct BfsParams {
   const uint8_t* vss_range; // row range of each VSS
   // per-call workspace
   uint32_t* vis;            // visited bits, n_words
-  uint8_t* mark;            // lazy: reached byte per vertex, 32 * n_words
+  uint8_t* mark;            // lazy: reached byte per vertex, 32 * n_words, then 64 padding bytes
   uint32_t* front;          // lazy: n_words; eager: 3 * n_words
   uint32_t* queue;          // 3 * qcap
   uint32_t* ctrl;           // kCtrlWords
