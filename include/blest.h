@@ -68,7 +68,7 @@ enum { BLEST_UPDATE_AUTO = 0, BLEST_UPDATE_EAGER = 1, BLEST_UPDATE_LAZY = 2 };
 
 typedef struct {
   uint32_t sigma;      /* slice width in columns: 8 (the paper's value), 16 or 32 */
-  uint32_t slots;      /* slices per lane of a 64-lane wavefront: tau = 64 * slots (1..8) */
+  uint32_t slots;      /* slices per lane of a 64-lane wavefront: tau = 64 * slots (1, 2, 4, 8; default 2) */
   uint32_t window;     /* Algorithm 1 window w, a multiple of sigma (default 65536) */
   int32_t reorder;     /* BLEST_REORDER_* */
   int32_t update;      /* BLEST_UPDATE_* */

@@ -142,7 +142,7 @@ class Graph:
     listing out-neighbours.  device=-1 builds the host structure only (statistics
     and exports work; BFS calls raise)."""
 
-    def __init__(self, csr, *, sigma=8, slots=4, window=1 << 16, reorder="auto", update="auto",
+    def __init__(self, csr, *, sigma=8, slots=2, window=1 << 16, reorder="auto", update="auto",
                  device=0, threads=0, block=0, blocks_per_cu=0, group=0, ranges=0, hubs="auto", lds_kib=0):
         o = default_options()
         o.sigma, o.slots, o.window = sigma, slots, window

@@ -86,25 +86,39 @@ struct VssGroup {
 };
 
 
-// Loads slot r of a VSS whose slices are [beg, end) for every lane.  The loads
-// are issued unconditionally (lanes past the end re-read slice beg, a line the
-// wavefront fetches anyway, and then drop it): with no branch around them the
-// compiler knows how many memory operations follow each load and can wait for
-// exactly the ones it needs instead of draining everything.
+// Raw buffer descriptor over `bytes` bytes at `base` (word 3: 32-bit data format,
+// as gfx9 raw buffers use).  Buffer loads past `bytes` return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, 0x00020000);
+}
+
+template <typename MT>
+__device__ __forceinline__ MT buffer_load_mask(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(MT) == 1) return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+  else if constexpr (sizeof(MT) == 2) return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+  else return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+// Loads the slots of a VSS whose slices are [beg, end) for every lane, through
+// buffer descriptors that span exactly the VSS: lanes past the end read zero (an
+// empty slice) with no clamp or select, the descriptor lives in scalar registers
+// and the slot offset goes into the instruction, so a slot costs no vector ALU
+// work.  The slices are streamed once per activation and are loaded
+// non-temporally, so that they do not evict the reached bytes and bitmaps that
+// the level keeps reusing.
 template <typename MT, int SLOTS, int G>
 __device__ __forceinline__ void load_vss(const BfsParams& p, uint32_t beg, uint32_t end, int k,
                                          VssGroup<MT, SLOTS, G>& g) {
   const MT* masks = static_cast<const MT*>(p.masks);
+  const uint32_t n = end - beg;
+  const __amdgpu_buffer_rsrc_t rr = buffer_of(p.row_ids + beg, n * 4u);
+  const __amdgpu_buffer_rsrc_t rm = buffer_of(masks + beg, n * (uint32_t)sizeof(MT));
   const uint32_t lane = lane_id();
+  constexpr int kSlc = 2;  // non-temporal (streaming) cache policy
 #pragma unroll
   for (int r = 0; r < SLOTS; ++r) {
-    const uint32_t idx = beg + lane + r * kWave;
-    const bool ok = idx < end;
-    const uint32_t at = ok ? idx : beg;
-    const MT mv = masks[at];
-    const uint32_t uv = p.row_ids[at];
-    g.m[k][r] = ok ? mv : MT(0);
-    g.u[k][r] = ok ? uv : 0u;
+    g.u[k][r] = __builtin_amdgcn_raw_buffer_load_b32(rr, (lane + r * kWave) * 4u, 0, kSlc);
+    g.m[k][r] = buffer_load_mask<MT>(rm, (lane + r * kWave) * (uint32_t)sizeof(MT));
   }
 }
 
@@ -122,11 +136,21 @@ __device__ __forceinline__ void load_group(const BfsParams& p, uint32_t mb, uint
   }
 }
 
-// Address of a reached byte to store 1 into: the row's own, or this lane's byte
-// in the padding past the array (never read) when no mark is due, so that the
-// store can be issued unconditionally.
-__device__ __forceinline__ uint8_t* mark_slot(const BfsParams& p, bool need, uint32_t u) {
-  return need ? p.mark + u : p.mark + 32ull * p.n_words + lane_id();
+// Stores 1 into a reached byte: the row's own, or, when no mark is due, this
+// lane's byte in the padding past the array (never read), so that the store is
+// issued unconditionally and the compiler's waits stay exact.  Each wavefront has
+// its own 64-byte pad line (kMarkPadLines of them): one line shared by the grid
+// would put every such store on the same L2 channel.  `pad` is
+// mark_pad_offset(p); offsets are 32-bit (the library caps n accordingly).
+__device__ __forceinline__ uint32_t mark_pad_offset(const BfsParams& p) {
+  const uint32_t line = ((blockIdx.x * blockDim.x + threadIdx.x) / kWave) & (kMarkPadLines - 1);
+  return 32u * p.n_words + 64u * line + lane_id();
+}
+__device__ __forceinline__ void store_mark(__amdgpu_buffer_rsrc_t mark, uint32_t pad, bool need, uint32_t u) {
+  __builtin_amdgcn_raw_buffer_store_b8((uint8_t)1, mark, need ? u : pad, 0, 0);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mark_buffer(const BfsParams& p) {
+  return buffer_of(p.mark, 32u * p.n_words + 64u * kMarkPadLines);
 }
 
 // Stage 1 driver shared by both schemes.  Wavefront w processes the queue
@@ -135,10 +159,11 @@ __device__ __forceinline__ uint8_t* mark_slot(const BfsParams& p, bool need, uin
 // l-th next position - VSS slice range and the sigma-bit frontier chunk alpha of
 // its slice set - so the dependent queue -> metadata -> frontier loads are paid
 // once per 64 VSSs; the values are then broadcast with readlane.  VSSs are taken
-// G at a time in three steps: issue(cur) starts the group's own loads (visited
-// words), the next group's slice loads follow, then finish(cur, issued) uses the
-// results; every step is free of branches around memory operations, so each wait
-// covers only the loads it needs.
+// G at a time, with two groups in flight: while one group's own loads (issue,
+// e.g. visited words) are waited for and applied (finish), the other group's
+// slice loads are outstanding; the buffers swap roles rather than being copied,
+// since a copy would wait for its loads.  Every step is free of branches around
+// memory operations, so each wait covers only the loads it needs.
 template <typename MT, int SLOTS, int G, class Issue, class Finish>
 __device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, uint32_t len, const uint32_t* fcur,
                                        Issue&& issue, Finish&& finish) {
@@ -156,13 +181,15 @@ __device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, u
       ma = frontier_chunk<SIG>(fcur, p.v2r[v]);
     }
     const uint32_t cnt = min((uint32_t)kWave, (len - base + nw - 1) / nw);
-    VssGroup<MT, SLOTS, G> cur, nxt;
-    load_group<MT, SLOTS, G>(p, mb, me, ma, 0, cnt, cur);
-    for (uint32_t k = 0; k < cnt; k += G) {
-      const auto issued = issue(cur);
-      load_group<MT, SLOTS, G>(p, mb, me, ma, k + G, cnt, nxt);  // empty past the end
-      finish(cur, issued);
-      cur = nxt;
+    VssGroup<MT, SLOTS, G> ga, gb;
+    load_group<MT, SLOTS, G>(p, mb, me, ma, 0, cnt, ga);
+    load_group<MT, SLOTS, G>(p, mb, me, ma, G, cnt, gb);  // empty past the end
+    for (uint32_t k = 0; k < cnt; k += 2 * G) {
+      finish(ga, issue(ga));
+      load_group<MT, SLOTS, G>(p, mb, me, ma, k + 2 * G, cnt, ga);
+      if (k + G >= cnt) break;
+      finish(gb, issue(gb));
+      load_group<MT, SLOTS, G>(p, mb, me, ma, k + 3 * G, cnt, gb);
     }
   }
 }
@@ -175,6 +202,8 @@ __device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, u
 template <typename MT, int SLOTS, int G>
 __device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* qc, uint32_t len) {
   using Words = struct { uint32_t w[G][SLOTS]; };
+  const __amdgpu_buffer_rsrc_t mrk = mark_buffer(p);
+  const uint32_t pad = mark_pad_offset(p);
   stage1<MT, SLOTS, G>(
       p, qc, len, p.front,
       [&](const VssGroup<MT, SLOTS, G>& g) {
@@ -195,7 +224,7 @@ __device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* 
           for (int r = 0; r < SLOTS; ++r) {
             const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
             const bool need = hit && !(cw.w[k][r] & (1u << (g.u[k][r] & 31)));
-            *mark_slot(p, need, g.u[k][r]) = 1;
+            store_mark(mrk, pad, need, g.u[k][r]);
           }
       });
 }
@@ -263,11 +292,12 @@ __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32
         load_vss<MT, SLOTS, G>(p, beg, end, k, g);
       }
     };
-    uint32_t src[G];
-    VssGroup<MT, SLOTS, G> cur, nxt;
-    take(src, cur);
-    while (src[0] < 64u) {
-      take(src, nxt);
+    const __amdgpu_buffer_rsrc_t mrk = mark_buffer(p);
+    const uint32_t pad = mark_pad_offset(p);
+    // Two groups are kept in flight: while one is applied, the slice loads of
+    // the other and of the group after it are outstanding.  The buffers swap
+    // roles instead of being copied, since a copy would wait for its loads.
+    auto apply = [&](const VssGroup<MT, SLOTS, G>& cur) {
       // cached hits: all LDS words first, then de-duplicating ORs where unvisited
       uint32_t lw[G][SLOTS];
       bool need[G][SLOTS];
@@ -284,22 +314,41 @@ __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32
           // make nearly every group wait for a load
           need[k][q] = hit && (!in || !(lw[k][q] & (1u << (cur.u[k][q] & 31))));
         }
+      // unvisited cached hits are rare on dense levels: one wavefront-wide test
+      // skips the per-slot de-duplication when the group has none
+      bool any_new = false;
 #pragma unroll
       for (int k = 0; k < G; ++k)
 #pragma unroll
-        for (int q = 0; q < SLOTS; ++q) {
-          const uint32_t wr = (cur.u[k][q] - rbase) >> 5;
-          if (need[k][q] && (wr & 63u) <= cmask) {
-            const uint32_t bit = 1u << (cur.u[k][q] & 31);
-            const uint32_t old = atomicOr(&lds[((wr >> 6) << cs) | (wr & 63u)], bit);
-            need[k][q] = !(old & bit);
+        for (int q = 0; q < SLOTS; ++q) any_new |= need[k][q] && ((((cur.u[k][q] - rbase) >> 5) & 63u) <= cmask);
+      if (__ballot(any_new)) {
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+#pragma unroll
+          for (int q = 0; q < SLOTS; ++q) {
+            const uint32_t wr = (cur.u[k][q] - rbase) >> 5;
+            if (need[k][q] && (wr & 63u) <= cmask) {
+              const uint32_t bit = 1u << (cur.u[k][q] & 31);
+              const uint32_t old = atomicOr(&lds[((wr >> 6) << cs) | (wr & 63u)], bit);
+              need[k][q] = !(old & bit);
+            }
           }
-        }
+      }
 #pragma unroll
       for (int k = 0; k < G; ++k)
 #pragma unroll
-        for (int q = 0; q < SLOTS; ++q) *mark_slot(p, need[k][q], cur.u[k][q]) = 1;
-      cur = nxt;
+        for (int q = 0; q < SLOTS; ++q) store_mark(mrk, pad, need[k][q], cur.u[k][q]);
+    };
+    uint32_t sa[G], sb[G];
+    VssGroup<MT, SLOTS, G> ga, gb;
+    take(sa, ga);
+    take(sb, gb);
+    while (sa[0] < 64u) {
+      apply(ga);
+      take(sa, ga);
+      if (sb[0] >= 64u) break;
+      apply(gb);
+      take(sb, gb);
     }
   }
 }
