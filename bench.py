@@ -308,7 +308,7 @@ def run_serve(args):
     src_of = lambda g, seed, k: inputs.sources(graphs[g], seed=seed, k=k)
     srv = Server(handles, budget, streams=2)
     # mean service time of a lone request (closed loop, one at a time)
-    probe = poisson_trace(99, 1.0, 40, names, src_of)
+    probe = poisson_trace(99, 1.0, 24, names, src_of)
     lone = []
     for t, gname, s in probe:
         r = srv.run([(0.0, gname, s)], realtime=False)[0]
@@ -317,7 +317,7 @@ def run_serve(args):
     log(f"[bench] mean lone service time {service * 1000:.2f} ms")
     edges_of = lambda r: sum(float(degs[r.graph][row >= 0].sum()) / 2.0 for row in r.levels.cpu().numpy())
     sweep = []
-    for rho in (0.1, 0.25, 0.5, 0.75, 0.9, 1.1):
+    for rho in (0.25, 0.5, 0.9):
         trace = poisson_trace(int(rho * 1000), rho / service, args.serve_requests, names, src_of)
         reqs = srv.run(trace)
         s = summarize(reqs, edges_of)
@@ -361,7 +361,7 @@ def main():
     ap.add_argument("--ranges", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

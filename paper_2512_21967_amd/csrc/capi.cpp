@@ -232,7 +232,7 @@ SingleWorkspace* single_workspace(blest_graph* g, void* stream, blest_status* st
   auto ws = std::make_unique<SingleWorkspace>();
   const size_t nw = g->n_words();
   hipError_t e = ws->vis.alloc(sizeof(uint32_t) * nw);
-  if (e == hipSuccess) e = ws->mark.alloc(32 * nw + 64 * kMarkPadLines);  // + never-read pad lines
+  if (e == hipSuccess) e = ws->mark.alloc(32 * nw);
   if (e == hipSuccess) e = ws->front.alloc(sizeof(uint32_t) * 3 * nw);
   if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 3 * std::max<size_t>(g->bvss.num_vss, 1));
   if (e == hipSuccess) e = ws->ctrl.alloc(sizeof(uint32_t) * kCtrlWords);
@@ -336,8 +336,8 @@ blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, cons
   *out = nullptr;
   if (n == 0 || !row_ptr || (nnz > 0 && !col_idx)) return BLEST_ERR_INVALID_ARGUMENT;
   if (nnz > 0xFFFFFFFFull) return BLEST_ERR_TOO_LARGE;
-  // reached bytes and their padding are addressed with 32-bit offsets
-  if (32ull * ((n + 31ull) / 32) + 64ull * kMarkPadLines > 0xFFFFFFFFull) return BLEST_ERR_TOO_LARGE;
+  // reached bytes are addressed with 32-bit offsets
+  if (32ull * ((n + 31ull) / 32) > 0xFFFFFFFFull) return BLEST_ERR_TOO_LARGE;
   blest_options o;
   blest_default_options(&o);
   if (opt) o = *opt;
@@ -700,7 +700,7 @@ blest_status blest_footprint(blest_handle h, uint32_t k, uint64_t* bytes) {
   const uint64_t q = 3ull * std::max<uint32_t>(h->bvss.num_vss, 1) * 4;
   uint64_t ws;
   if (k == 1)
-    ws = 4 * nw * 4 + 32 * nw + 64 * kMarkPadLines + q + kCtrlWords * 4;
+    ws = 4 * nw * 4 + 32 * nw + q + kCtrlWords * 4;
   else
     ws = 3ull * h->n * 8 + q + kCtrlWords * 4;  // 64-bit frontier/visited rows
   *bytes = ws + (uint64_t)k * h->n * 4;

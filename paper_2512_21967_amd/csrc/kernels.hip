@@ -136,21 +136,14 @@ __device__ __forceinline__ void load_group(const BfsParams& p, uint32_t mb, uint
   }
 }
 
-// Stores 1 into a reached byte: the row's own, or, when no mark is due, this
-// lane's byte in the padding past the array (never read), so that the store is
-// issued unconditionally and the compiler's waits stay exact.  Each wavefront has
-// its own 64-byte pad line (kMarkPadLines of them): one line shared by the grid
-// would put every such store on the same L2 channel.  `pad` is
-// mark_pad_offset(p); offsets are 32-bit (the library caps n accordingly).
-__device__ __forceinline__ uint32_t mark_pad_offset(const BfsParams& p) {
-  const uint32_t line = ((blockIdx.x * blockDim.x + threadIdx.x) / kWave) & (kMarkPadLines - 1);
-  return 32u * p.n_words + 64u * line + lane_id();
-}
-__device__ __forceinline__ void store_mark(__amdgpu_buffer_rsrc_t mark, uint32_t pad, bool need, uint32_t u) {
-  __builtin_amdgcn_raw_buffer_store_b8((uint8_t)1, mark, need ? u : pad, 0, 0);
+// Stores 1 into row u's reached byte when a mark is due.  The store is masked
+// per lane, not redirected: redirecting the lanes with no mark to padding lines
+// (to keep the store unconditional) cost more in write traffic than it saved.
+__device__ __forceinline__ void store_mark(__amdgpu_buffer_rsrc_t mark, bool need, uint32_t u) {
+  if (need) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)1, mark, u, 0, 0);
 }
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t mark_buffer(const BfsParams& p) {
-  return buffer_of(p.mark, 32u * p.n_words + 64u * kMarkPadLines);
+  return buffer_of(p.mark, 32u * p.n_words);
 }
 
 // Stage 1 driver shared by both schemes.  Wavefront w processes the queue
@@ -203,7 +196,6 @@ template <typename MT, int SLOTS, int G>
 __device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* qc, uint32_t len) {
   using Words = struct { uint32_t w[G][SLOTS]; };
   const __amdgpu_buffer_rsrc_t mrk = mark_buffer(p);
-  const uint32_t pad = mark_pad_offset(p);
   stage1<MT, SLOTS, G>(
       p, qc, len, p.front,
       [&](const VssGroup<MT, SLOTS, G>& g) {
@@ -224,7 +216,7 @@ __device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* 
           for (int r = 0; r < SLOTS; ++r) {
             const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
             const bool need = hit && !(cw.w[k][r] & (1u << (g.u[k][r] & 31)));
-            store_mark(mrk, pad, need, g.u[k][r]);
+            store_mark(mrk, need, g.u[k][r]);
           }
       });
 }
@@ -256,9 +248,22 @@ __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32
   const uint32_t rw = p.range_len >> 5;  // words per range
   const uint32_t w0 = r * rw;
   const uint32_t cs = p.lds_cshift, cmask = (1u << cs) - 1u;
-  for (uint32_t i = threadIdx.x; i < p.range_words; i += blockDim.x) {
-    const uint32_t wr = ((i >> cs) << 6) | (i & cmask);
-    lds[i] = (wr < rw && w0 + wr < p.n_words) ? p.vis[w0 + wr] : 0u;
+  {
+    // eight independent loads per thread and step (a load-then-store loop would
+    // wait for each load in turn); words past the range read zero
+    const uint32_t have = w0 < p.n_words ? min(rw, p.n_words - w0) : 0u;
+    const __amdgpu_buffer_rsrc_t vb = buffer_of(p.vis + w0, have * 4u);
+    for (uint32_t b = threadIdx.x; b < p.range_words; b += 8 * blockDim.x) {
+      uint32_t v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t i = b + j * blockDim.x;
+        v[j] = __builtin_amdgcn_raw_buffer_load_b32(vb, (((i >> cs) << 6) | (i & cmask)) * 4u, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (b + j * blockDim.x < p.range_words) lds[b + j * blockDim.x] = v[j];
+    }
   }
   __syncthreads();
   const uint32_t lane = lane_id();
@@ -293,10 +298,9 @@ __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32
       }
     };
     const __amdgpu_buffer_rsrc_t mrk = mark_buffer(p);
-    const uint32_t pad = mark_pad_offset(p);
-    // Two groups are kept in flight: while one is applied, the slice loads of
-    // the other and of the group after it are outstanding.  The buffers swap
-    // roles instead of being copied, since a copy would wait for its loads.
+    // Three groups are kept in flight: while one is applied, the slice loads of
+    // the next two are outstanding.  The buffers rotate roles instead of being
+    // copied, since a copy would wait for its loads.
     auto apply = [&](const VssGroup<MT, SLOTS, G>& cur) {
       // cached hits: all LDS words first, then de-duplicating ORs where unvisited
       uint32_t lw[G][SLOTS];
@@ -337,18 +341,22 @@ __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32
 #pragma unroll
       for (int k = 0; k < G; ++k)
 #pragma unroll
-        for (int q = 0; q < SLOTS; ++q) store_mark(mrk, pad, need[k][q], cur.u[k][q]);
+        for (int q = 0; q < SLOTS; ++q) store_mark(mrk, need[k][q], cur.u[k][q]);
     };
-    uint32_t sa[G], sb[G];
-    VssGroup<MT, SLOTS, G> ga, gb;
+    uint32_t sa[G], sb[G], sc[G];
+    VssGroup<MT, SLOTS, G> ga, gb, gc;
     take(sa, ga);
     take(sb, gb);
+    take(sc, gc);
     while (sa[0] < 64u) {
       apply(ga);
       take(sa, ga);
       if (sb[0] >= 64u) break;
       apply(gb);
       take(sb, gb);
+      if (sc[0] >= 64u) break;
+      apply(gc);
+      take(sc, gc);
     }
   }
 }

@@ -27,7 +27,7 @@ struct BfsParams {
   const uint8_t* vss_range; // row range of each VSS
   // per-call workspace
   uint32_t* vis;            // visited bits, n_words
-  uint8_t* mark;            // lazy: reached byte per vertex, 32 * n_words, then 64 * kMarkPadLines padding bytes
+  uint8_t* mark;            // lazy: reached byte per vertex, 32 * n_words
   uint32_t* front;          // lazy: n_words; eager: 3 * n_words
   uint32_t* queue;          // 3 * qcap
   uint32_t* ctrl;           // kCtrlWords
@@ -40,10 +40,6 @@ struct BfsParams {
   uint32_t lds_cshift;      // the cache holds words 0 .. 2^lds_cshift - 1 of every 64-word chunk
   uint32_t lds_min_len;     // lazy: levels with fewer queue entries skip the LDS cache
 };
-
-// Never-read padding after the reached bytes: one 64-byte line per wavefront
-// (modulo kMarkPadLines) takes the stores of lanes with no mark due.
-constexpr uint32_t kMarkPadLines = 1024;
 
 // Queue entries carry the VSS's row range in their low bits.
 constexpr uint32_t kRangeBits = 5;
