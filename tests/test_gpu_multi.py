@@ -116,3 +116,13 @@ def test_batched_config_s20_k64_sampled_rows():
     reached = got >= 0
     for j in range(64):
         assert np.array_equal(reached[j], reached[0]) or not np.any(reached[j] & reached[0])
+
+
+@pytest.mark.parametrize("slots", [1, 4])
+def test_high_diameter_grid(slots):
+    """A grid with hundreds of levels (RCM ordering): many k-source levels with
+    small frontiers per source."""
+    gr = inputs.grid_workload(96, 0.9, seed=4, permute_seed=5)
+    g = blest.Graph(gr, reorder="bandwidth", slots=slots)
+    srcs = inputs.sources(gr, seed=9, k=40)
+    np.testing.assert_array_equal(run_multi(g, srcs), oracle.bfs_multi(gr, srcs))
