@@ -234,7 +234,8 @@ SingleWorkspace* single_workspace(blest_graph* g, void* stream, blest_status* st
   hipError_t e = ws->vis.alloc(sizeof(uint32_t) * nw);
   if (e == hipSuccess) e = ws->mark.alloc(32 * nw);
   if (e == hipSuccess) e = ws->front.alloc(sizeof(uint32_t) * 3 * nw);
-  if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 3 * std::max<size_t>(g->bvss.num_vss, 1));
+  // queues: eager 3 x 32-bit entries, lazy 2 x 64-bit entries (VSS, alpha)
+  if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 4 * std::max<size_t>(g->bvss.num_vss, 1));
   if (e == hipSuccess) e = ws->ctrl.alloc(sizeof(uint32_t) * kCtrlWords);
   if (e == hipSuccess) e = hipMemset(ws->ctrl.p, 0, sizeof(uint32_t) * kCtrlWords);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -697,7 +698,7 @@ blest_status blest_footprint(blest_handle h, uint32_t k, uint64_t* bytes) {
     return BLEST_OK;
   }
   const uint64_t nw = h->n_words();
-  const uint64_t q = 3ull * std::max<uint32_t>(h->bvss.num_vss, 1) * 4;
+  const uint64_t q = 4ull * std::max<uint32_t>(h->bvss.num_vss, 1) * 4;
   uint64_t ws;
   if (k == 1)
     ws = 4 * nw * 4 + 32 * nw + q + kCtrlWords * 4;

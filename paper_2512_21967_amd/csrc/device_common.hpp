@@ -80,25 +80,26 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane) {
 }
 
 struct PlainEntry {
-  __device__ uint32_t operator()(uint32_t v) const { return v; }
+  __device__ uint32_t operator()(uint32_t v, uint32_t) const { return v; }
 };
 
 // Writes a lane's VSS ranges [vb[i], vb[i] + vn[i]) for i < SETS (vn[i] = 0: none)
-// at qn[pos ...], in order; cnt is the sum of vn.  Lanes with at most kSmallPush
-// entries write their own; longer pushes (hub slice sets own thousands of VSSs)
-// are written by the whole wavefront, 4 x 64 entries per step, lane after lane.
-// The ranges arrive in registers, so the wavefront-wide part issues no load
-// besides what the encoder `enc` (VSS ID -> queue entry) reads.  Every lane of
-// the wavefront must call this.
+// at qn[pos ...], in order; cnt is the sum of vn.  Entry x of range i is
+// enc(vb[i] + x, vt[i]) (vt: a per-range tag, e.g. the set's frontier chunk).
+// Lanes with at most kSmallPush entries write their own; longer pushes (hub
+// slice sets own thousands of VSSs) are written by the whole wavefront, 4 x 64
+// entries per step, lane after lane.  The ranges arrive in registers, so the
+// wavefront-wide part issues no load besides what the encoder reads.  Every
+// lane of the wavefront must call this.
 constexpr uint32_t kSmallPush = 8;
-template <int SETS, class Enc = PlainEntry>
-__device__ __forceinline__ void wave_push(uint32_t* qn, uint32_t pos, uint32_t cnt, const uint32_t (&vb)[SETS],
-                                          const uint32_t (&vn)[SETS], Enc enc = Enc()) {
+template <int SETS, class Q, class Enc>
+__device__ __forceinline__ void wave_push(Q* qn, uint32_t pos, uint32_t cnt, const uint32_t (&vb)[SETS],
+                                          const uint32_t (&vn)[SETS], const uint32_t (&vt)[SETS], Enc enc) {
   const bool small = cnt <= kSmallPush;
   if (small && cnt) {
 #pragma unroll
     for (int i = 0; i < SETS; ++i)
-      for (uint32_t v = vb[i]; v < vb[i] + vn[i]; ++v) qn[pos++] = enc(v);
+      for (uint32_t v = vb[i]; v < vb[i] + vn[i]; ++v) qn[pos++] = enc(v, vt[i]);
   }
   uint64_t big = __ballot(!small);
   while (big) {
@@ -110,12 +111,13 @@ __device__ __forceinline__ void wave_push(uint32_t* qn, uint32_t pos, uint32_t c
       const uint32_t n = readlane(vn[i], l);
       if (n == 0) continue;
       const uint32_t b = readlane(vb[i], l);
+      const uint32_t tag = readlane(vt[i], l);
       for (uint32_t x0 = 0; x0 < n; x0 += 4 * kWave) {
-        uint32_t val[4];
+        Q val[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const uint32_t x = x0 + j * kWave + lane_id();
-          val[j] = x < n ? enc(b + x) : 0u;
+          val[j] = enc(b + (x < n ? x : 0u), tag);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -126,6 +128,16 @@ __device__ __forceinline__ void wave_push(uint32_t* qn, uint32_t pos, uint32_t c
       lp += n;
     }
   }
+}
+
+// Plain VSS-ID pushes (no tag).
+template <int SETS>
+__device__ __forceinline__ void wave_push(uint32_t* qn, uint32_t pos, uint32_t cnt, const uint32_t (&vb)[SETS],
+                                          const uint32_t (&vn)[SETS]) {
+  uint32_t vt[SETS];
+#pragma unroll
+  for (int i = 0; i < SETS; ++i) vt[i] = 0;
+  wave_push<SETS>(qn, pos, cnt, vb, vn, vt, PlainEntry{});
 }
 
 }  // namespace

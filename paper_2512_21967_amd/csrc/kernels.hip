@@ -36,17 +36,30 @@
 namespace blest {
 namespace {
 
-// Queue entry of VSS v: its ID and row range.
-// Queue entry of VSS v: (v << kRangeBits) | row range.  With one range the table
-// is not read (vss_range == nullptr), so pushes carry no load.
+// Queue entry of VSS v (eager scheme): (v << kRangeBits) | row range.  With one
+// range the table is not read (vss_range == nullptr), so pushes carry no load.
 struct RangeEntry {
   const uint8_t* vss_range;
-  __device__ uint32_t operator()(uint32_t v) const {
+  __device__ uint32_t operator()(uint32_t v, uint32_t) const {
     return vss_range ? (v << kRangeBits) | vss_range[v] : v << kRangeBits;
   }
 };
 __device__ __forceinline__ RangeEntry range_entry(const BfsParams& p) {
   return RangeEntry{p.nranges > 1 ? p.vss_range : nullptr};
+}
+
+// Queue entry of VSS v (lazy scheme): x = (v << kRangeBits) | row range, y = the
+// sigma-bit frontier chunk alpha of v's slice set.  Stage 2 knows a set's final
+// chunk when it queues the set, so Stage 1 reads alpha from the entry instead of
+// following VSS -> set -> frontier bitmap.
+struct LazyEntry {
+  const uint8_t* vss_range;
+  __device__ uint2 operator()(uint32_t v, uint32_t alpha) const {
+    return make_uint2(vss_range ? (v << kRangeBits) | vss_range[v] : v << kRangeBits, alpha);
+  }
+};
+__device__ __forceinline__ LazyEntry lazy_entry(const BfsParams& p) {
+  return LazyEntry{p.nranges > 1 ? p.vss_range : nullptr};
 }
 
 __device__ __forceinline__ uint32_t to_orig(const BfsParams& p, uint32_t u) {
@@ -150,17 +163,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t mark_buffer(const BfsParams& p
 // positions w, w + nw, w + 2 nw, ... (round-robin over all wavefronts of the
 // grid, Section 2.1.1).  Lane l first fetches the metadata of the wavefront's
 // l-th next position - VSS slice range and the sigma-bit frontier chunk alpha of
-// its slice set - so the dependent queue -> metadata -> frontier loads are paid
-// once per 64 VSSs; the values are then broadcast with readlane.  VSSs are taken
+// its slice set (from the lazy queue entry, or the eager frontier bitmap) - so
+// the dependent queue -> metadata loads are paid once per 64 VSSs; the values are then broadcast with readlane.  VSSs are taken
 // G at a time, with two groups in flight: while one group's own loads (issue,
 // e.g. visited words) are waited for and applied (finish), the other group's
 // slice loads are outstanding; the buffers swap roles rather than being copied,
 // since a copy would wait for its loads.  Every step is free of branches around
 // memory operations, so each wait covers only the loads it needs.
-template <typename MT, int SLOTS, int G, class Issue, class Finish>
-__device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, uint32_t len, const uint32_t* fcur,
-                                       Issue&& issue, Finish&& finish) {
-  constexpr int SIG = 8 * sizeof(MT);
+// `entry(pos, alpha)` returns the VSS at queue position pos and sets its alpha.
+template <typename MT, int SLOTS, int G, class Entry, class Issue, class Finish>
+__device__ __forceinline__ void stage1(const BfsParams& p, uint32_t len, Entry&& entry, Issue&& issue,
+                                       Finish&& finish) {
   const uint32_t lane = lane_id();
   const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const uint32_t nw = (gridDim.x * blockDim.x) / kWave;
@@ -168,10 +181,9 @@ __device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, u
     const uint32_t pos = base + lane * nw;
     uint32_t mb = 0, me = 0, ma = 0;
     if (pos < len) {
-      const uint32_t v = qc[pos] >> kRangeBits;
+      const uint32_t v = entry(pos, ma);
       mb = p.vss_beg[v];
       me = p.vss_beg[v + 1];
-      ma = frontier_chunk<SIG>(fcur, p.v2r[v]);
     }
     const uint32_t cnt = min((uint32_t)kWave, (len - base + nw - 1) / nw);
     VssGroup<MT, SLOTS, G> ga, gb;
@@ -193,11 +205,16 @@ __device__ __forceinline__ void stage1(const BfsParams& p, const uint32_t* qc, u
 // stores are idempotent and all write the same value, so no read-modify-write is
 // needed (device-scope atomic ORs cost an order of magnitude more on MI355X).
 template <typename MT, int SLOTS, int G>
-__device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* qc, uint32_t len) {
+__device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint2* qc, uint32_t len) {
   using Words = struct { uint32_t w[G][SLOTS]; };
   const __amdgpu_buffer_rsrc_t mrk = mark_buffer(p);
   stage1<MT, SLOTS, G>(
-      p, qc, len, p.front,
+      p, len,
+      [&](uint32_t pos, uint32_t& alpha) {
+        const uint2 e = qc[pos];
+        alpha = e.y;
+        return e.x >> kRangeBits;
+      },
       [&](const VssGroup<MT, SLOTS, G>& g) {
         Words cw;
 #pragma unroll
@@ -237,7 +254,7 @@ __device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint32_t* 
 // every group of slices wait for a load when hot and cold rows are interleaved.
 // A mark is a one-byte store into the row's reached byte.
 template <typename MT, int SLOTS, int G>
-__device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32_t* qc, uint32_t len, uint32_t* lds) {
+__device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint2* qc, uint32_t len, uint32_t* lds) {
   if (len < p.lds_min_len) {
     stage1_lazy<MT, SLOTS, G>(p, qc, len);
     return;
@@ -273,15 +290,15 @@ __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32
   const uint32_t rbase = r * p.range_len;
   for (uint32_t base = wg; base < len; base += nwg * kWave) {
     const uint32_t pos = base + lane * nwg;
-    const uint32_t e = pos < len ? qc[pos] : 0u;
-    const bool mine = pos < len && (e & (kMaxRanges - 1)) == r;
+    const uint2 e = pos < len ? qc[pos] : make_uint2(0u, 0u);
+    const bool mine = pos < len && (e.x & (kMaxRanges - 1)) == r;
     uint64_t pick = __ballot(mine);
     uint32_t mb = 0, me = 0, ma = 0;
     if (mine) {
-      const uint32_t v = e >> kRangeBits;
+      const uint32_t v = e.x >> kRangeBits;
       mb = p.vss_beg[v];
       me = p.vss_beg[v + 1];
-      ma = frontier_chunk<SIG>(p.front, p.v2r[v]);
+      ma = e.y;
     }
     // G picked lanes at a time (uniform); missing ones read an empty VSS.  The
     // next group's slice loads are issued before the current group is applied.
@@ -366,7 +383,7 @@ __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint32
 // atomic add by thread 0): a reservation per wavefront would put thousands of
 // atomics on one counter per level.
 template <int SIG>
-__device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, uint32_t* qlen, int32_t level) {
+__device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint2* qn, uint32_t* qlen, int32_t level) {
   constexpr int SPW = 32 / SIG;  // slice sets per word
   __shared__ uint32_t s_wave[kMaxWaves];
   __shared__ uint32_t s_base;
@@ -377,9 +394,9 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, ui
   // spread over many workgroups instead of loading the first few.
   for (uint32_t b0 = 0; b0 < p.n_words; b0 += gridDim.x * blockDim.x) {
     const uint32_t t = b0 + (wave * gridDim.x + blockIdx.x) * kWave + lane;
-    uint32_t cnt = 0, vb[SPW], vn[SPW];
+    uint32_t cnt = 0, vb[SPW], vn[SPW], va[SPW];
 #pragma unroll
-    for (int i = 0; i < SPW; ++i) vb[i] = vn[i] = 0;
+    for (int i = 0; i < SPW; ++i) vb[i] = vn[i] = va[i] = 0;
     if (t < p.n_words) {
       // the 32 reached bytes of word t, folded into one bit each
       const uint4* mb = reinterpret_cast<const uint4*>(p.mark + 32ull * t);
@@ -396,7 +413,6 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, ui
       const uint32_t diff = reached & ~cur;
       if (diff) {
         p.vis[t] = cur | diff;
-        p.front[t] = diff;
         // levels of the new vertices: their original IDs are loaded 8 at a time
         // (two 16-byte loads) so that the stores do not wait one by one
 #pragma unroll
@@ -418,7 +434,8 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, ui
         }
 #pragma unroll
         for (int i = 0; i < SPW; ++i) {
-          if ((diff >> (i * SIG)) & chunk_mask<SIG>()) {
+          va[i] = (diff >> (i * SIG)) & chunk_mask<SIG>();
+          if (va[i]) {
             const uint32_t ss = t * SPW + i;
             vb[i] = p.real_ptrs[ss];
             vn[i] = p.real_ptrs[ss + 1] - vb[i];
@@ -441,7 +458,7 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint32_t* qn, ui
     }
     __syncthreads();
     const uint32_t pos = s_base + s_wave[wave] + incl - cnt;
-    wave_push<SPW>(qn, pos, cnt, vb, vn, range_entry(p));
+    wave_push<SPW>(qn, pos, cnt, vb, vn, va, lazy_entry(p));
     __syncthreads();
   }
 }
@@ -467,7 +484,12 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
       }
     return vw;
   };
-  stage1<MT, SLOTS, G>(p, qc, len, fc, issue, [&](const VssGroup<MT, SLOTS, G>& g, const Words& vw_) {
+  auto entry = [&](uint32_t pos, uint32_t& alpha) {
+    const uint32_t v = qc[pos] >> kRangeBits;
+    alpha = frontier_chunk<SIG>(fc, p.v2r[v]);
+    return v;
+  };
+  stage1<MT, SLOTS, G>(p, len, entry, issue, [&](const VssGroup<MT, SLOTS, G>& g, const Words& vw_) {
     const auto& vw = vw_.w;
     uint32_t cnt = 0, vb[G * SLOTS], vn[G * SLOTS];
 #pragma unroll
@@ -497,7 +519,7 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
     uint32_t total;
     const uint32_t pos = wave_reserve(qlen, cnt, total);
     if (total != 0)
-      wave_push<G * SLOTS>(qn, pos, cnt, vb, vn, range_entry(p));
+      wave_push<G * SLOTS>(qn, pos, cnt, vb, vn, vb /* tags: unused */, range_entry(p));
   });
 }
 
@@ -533,7 +555,6 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
     for (uint32_t t = tid; t < p.n_words; t += nt) {
       const uint32_t b = (t == sw) ? sbit : 0u;
       p.vis[t] = b;
-      p.front[t] = b;
       // the word's 32 reached bytes: zero, except the source's
       uint32_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (t == sw) z[(p.src & 31) >> 2] = 1u << (8 * (p.src & 3));
@@ -550,7 +571,12 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
       p.front[2 * p.n_words + t] = 0;
     }
   }
-  for (uint32_t j = tid; j < q0n; j += nt) p.queue[j] = range_entry(p)(q0b + j);
+  if (LAZY) {
+    const uint32_t a0 = 1u << (p.src % SIG);  // the source's bit in its set's frontier chunk
+    for (uint32_t j = tid; j < q0n; j += nt) reinterpret_cast<uint2*>(p.queue)[j] = lazy_entry(p)(q0b + j, a0);
+  } else {
+    for (uint32_t j = tid; j < q0n; j += nt) p.queue[j] = range_entry(p)(q0b + j, 0u);
+  }
   if (tid == 0) {
     qlen[0] = q0n;
     qlen[kLine] = 0;
@@ -561,8 +587,8 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
 
   for (int32_t level = 1; level <= (int32_t)p.n + 1; ++level) {
     if (LAZY) {
-      const uint32_t* qc = p.queue + ((level - 1) & 1) * p.qcap;
-      uint32_t* qn = p.queue + (level & 1) * p.qcap;
+      const uint2* qc = reinterpret_cast<const uint2*>(p.queue) + ((level - 1) & 1) * p.qcap;
+      uint2* qn = reinterpret_cast<uint2*>(p.queue) + (level & 1) * p.qcap;
       const uint32_t len = ld_relaxed(qlen + ((level - 1) % 3) * kLine);
       uint32_t* qnext_len = qlen + (level % 3) * kLine;
       if (tid == 0) __hip_atomic_store(qlen + ((level + 1) % 3) * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -28,8 +28,8 @@ struct BfsParams {
   // per-call workspace
   uint32_t* vis;            // visited bits, n_words
   uint8_t* mark;            // lazy: reached byte per vertex, 32 * n_words
-  uint32_t* front;          // lazy: n_words; eager: 3 * n_words
-  uint32_t* queue;          // 3 * qcap
+  uint32_t* front;          // eager: 3 * n_words (the lazy scheme keeps alpha in its queue entries)
+  uint32_t* queue;          // eager: 3 * qcap 32-bit entries; lazy: 2 * qcap 64-bit entries (VSS, alpha)
   uint32_t* ctrl;           // kCtrlWords
   int32_t* levels;          // n, original IDs
   uint32_t n, n_words, num_sets, num_vss, qcap;
