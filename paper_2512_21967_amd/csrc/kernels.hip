@@ -472,25 +472,35 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
                                              const uint32_t* fc, uint32_t* fn, uint32_t* qn, uint32_t* qlen,
                                              int32_t level) {
   constexpr int SIG = 8 * sizeof(MT);
-  using Words = struct { uint32_t w[G][SLOTS]; };
+  struct Pre {
+    uint32_t w[G][SLOTS], o[G][SLOTS], rb[G][SLOTS], re[G][SLOTS];
+  };
+  // Besides the visited words, a hit's original ID and its set's VSS range are
+  // loaded up front, in parallel, so that neither the level store nor the push
+  // waits for a further load after the claim (high-diameter graphs are bound by
+  // this chain's length, one level after another).
   auto issue = [&](const VssGroup<MT, SLOTS, G>& g) {
-    Words vw;
+    Pre pre;
 #pragma unroll
     for (int k = 0; k < G; ++k)
 #pragma unroll
       for (int r = 0; r < SLOTS; ++r) {
         const bool hit = ((uint32_t)g.m[k][r] & g.alpha[k]) != 0;
-        vw.w[k][r] = p.vis[hit ? (g.u[k][r] >> 5) : 0u];
+        const uint32_t x = hit ? g.u[k][r] : 0u;
+        pre.w[k][r] = p.vis[x >> 5];
+        pre.o[k][r] = to_orig(p, x);
+        pre.rb[k][r] = p.real_ptrs[x / SIG];
+        pre.re[k][r] = p.real_ptrs[x / SIG + 1];
       }
-    return vw;
+    return pre;
   };
   auto entry = [&](uint32_t pos, uint32_t& alpha) {
     const uint32_t v = qc[pos] >> kRangeBits;
     alpha = frontier_chunk<SIG>(fc, p.v2r[v]);
     return v;
   };
-  stage1<MT, SLOTS, G>(p, len, entry, issue, [&](const VssGroup<MT, SLOTS, G>& g, const Words& vw_) {
-    const auto& vw = vw_.w;
+  stage1<MT, SLOTS, G>(p, len, entry, issue, [&](const VssGroup<MT, SLOTS, G>& g, const Pre& pre) {
+    const auto& vw = pre.w;
     uint32_t cnt = 0, vb[G * SLOTS], vn[G * SLOTS];
 #pragma unroll
     for (int i = 0; i < G * SLOTS; ++i) vb[i] = vn[i] = 0;
@@ -505,12 +515,11 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
           const uint32_t old = atomicOr(fn + (x >> 5), bit);
           if (!(old & bit)) {
             atomicOr(p.vis + (x >> 5), bit);
-            p.levels[to_orig(p, x)] = level;
+            p.levels[pre.o[k][r]] = level;
             const uint32_t sh = (x & 31) & ~(uint32_t)(SIG - 1);
             if (((old >> sh) & chunk_mask<SIG>()) == 0) {
-              const uint32_t ss = x / SIG;
-              vb[k * SLOTS + r] = p.real_ptrs[ss];
-              vn[k * SLOTS + r] = p.real_ptrs[ss + 1] - vb[k * SLOTS + r];
+              vb[k * SLOTS + r] = pre.rb[k][r];
+              vn[k * SLOTS + r] = pre.re[k][r] - pre.rb[k][r];
               cnt += vn[k * SLOTS + r];
             }
           }
@@ -528,7 +537,10 @@ template <int SIG>
 __device__ __forceinline__ void clear_chunks(const BfsParams& p, uint32_t* f, const uint32_t* qold, uint32_t len) {
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nt = gridDim.x * blockDim.x;
-  for (uint32_t i = tid; i < len; i += nt) {
+  // the highest-numbered threads take the clears: on the small levels of
+  // high-diameter graphs they have no Stage 1 work, so the clears' dependent loads
+  // stay off the Stage 1 chain of the low-numbered wavefronts
+  for (uint32_t i = nt - 1 - tid; i < len; i += nt) {
     const uint32_t ss = p.v2r[qold[i] >> kRangeBits];
     if (SIG == 8) reinterpret_cast<uint8_t*>(f)[ss] = 0;
     else if (SIG == 16) reinterpret_cast<uint16_t*>(f)[ss] = 0;
