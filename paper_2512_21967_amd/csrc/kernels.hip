@@ -463,10 +463,16 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint2* qn, uint3
   }
 }
 
+// Entries of a wavefront's list of VSS ranges to queue (eager scheme).
+constexpr uint32_t kPushList = 64;
+
 // Stage 1 of the eager scheme: a hit whose vertex is not yet visited claims it with
 // a returning atomic OR on the next frontier; the claimer marks it visited, writes
-// its level, and - if it is the first claimer in its slice set's chunk - pushes the
-// set's VSS range (one queue reservation per wavefront and group).
+// its level, and - if it is the first claimer in its slice set's chunk - queues the
+// set's VSS range.  Ranges collect in per-wavefront lists in LDS and the workgroup
+// reserves queue space once at the end: on high-diameter graphs, where a level has
+// a few thousand claims, a reservation per wavefront put thousands of returning
+// atomics on one counter, serialised, into every level.
 template <typename MT, int SLOTS, int G>
 __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t* qc, uint32_t len,
                                              const uint32_t* fc, uint32_t* fn, uint32_t* qn, uint32_t* qlen,
@@ -474,6 +480,51 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
   constexpr int SIG = 8 * sizeof(MT);
   struct Pre {
     uint32_t w[G][SLOTS], o[G][SLOTS], rb[G][SLOTS], re[G][SLOTS];
+  };
+  // per-wavefront lists of VSS ranges to queue (first VSS, count)
+  __shared__ uint32_t s_pb[kMaxWaves][kPushList], s_pn[kMaxWaves][kPushList];
+  __shared__ uint32_t s_cnt[kMaxWaves], s_tot[kMaxWaves];
+  __shared__ uint32_t s_qbase;
+  const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+  if (lane == 0) s_cnt[wave] = 0;
+  // queues this wavefront's list with one reservation and empties it
+  auto flush_list = [&]() {
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t c = s_cnt[wave];
+    uint32_t b[1] = {0}, n[1] = {0};
+    if (lane < c) {
+      b[0] = s_pb[wave][lane];
+      n[0] = s_pn[wave][lane];
+    }
+    uint32_t total;
+    const uint32_t pos = wave_reserve(qlen, n[0], total);
+    wave_push<1>(qn, pos, n[0], b, n, b /* tags: unused */, range_entry(p));
+    if (lane == 0) s_cnt[wave] = 0;
+  };
+  // queues every wavefront's list with one reservation for the workgroup
+  auto flush_block = [&]() {
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t c = s_cnt[wave];
+    uint32_t b[1] = {0}, n[1] = {0};
+    if (lane < c) {
+      b[0] = s_pb[wave][lane];
+      n[0] = s_pn[wave][lane];
+    }
+    const uint32_t incl = wave_inclusive_scan(n[0]);
+    if (lane == kWave - 1) s_tot[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t run = 0;
+      for (uint32_t w = 0; w < nwaves; ++w) {
+        const uint32_t x = s_tot[w];
+        s_tot[w] = run;
+        run += x;
+      }
+      s_qbase = run ? atomicAdd(qlen, run) : 0u;
+    }
+    __syncthreads();
+    wave_push<1>(qn, s_qbase + s_tot[wave] + incl - n[0], n[0], b, n, b /* tags: unused */, range_entry(p));
   };
   // Besides the visited words, a hit's original ID and its set's VSS range are
   // loaded up front, in parallel, so that neither the level store nor the push
@@ -525,11 +576,37 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
           }
         }
       }
-    uint32_t total;
-    const uint32_t pos = wave_reserve(qlen, cnt, total);
-    if (total != 0)
+    // Queue the new sets' VSS ranges: appended to this wavefront's list in LDS
+    // and reserved once per workgroup after the loop; a group with more ranges
+    // than the list holds, or a full list, takes a wavefront reservation now.
+    uint32_t nr = 0;
+#pragma unroll
+    for (int i = 0; i < G * SLOTS; ++i) nr += vn[i] != 0;
+    const uint32_t rincl = wave_inclusive_scan(nr);
+    const uint32_t rtot = __shfl(rincl, kWave - 1, kWave);
+    if (rtot == 0) return;
+    uint32_t used = s_cnt[wave];
+    if (used + rtot > kPushList) {
+      flush_list();
+      used = 0;
+    }
+    if (rtot > kPushList) {
+      uint32_t total;
+      const uint32_t pos = wave_reserve(qlen, cnt, total);
       wave_push<G * SLOTS>(qn, pos, cnt, vb, vn, vb /* tags: unused */, range_entry(p));
+      return;
+    }
+    uint32_t at = used + rincl - nr;
+#pragma unroll
+    for (int i = 0; i < G * SLOTS; ++i)
+      if (vn[i]) {
+        s_pb[wave][at] = vb[i];
+        s_pn[wave][at] = vn[i];
+        ++at;
+      }
+    if (lane == 0) s_cnt[wave] = used + rtot;
   });
+  flush_block();
 }
 
 // Clears the frontier chunks of the sets named by queue qold (eager scheme).
