@@ -49,7 +49,7 @@ struct SingleWorkspace {
 // Per-stream scratch of the k-source kernel: 64-bit visited pairs and frontier
 // words per vertex, two queues, control block.
 struct MultiWorkspace {
-  DevBuf vis, front, queue, ctrl;
+  DevBuf vis, front, touched, queue, ctrl;
 };
 
 // Persistent launches are serialised device-wide: two persistent grids that each
@@ -256,6 +256,7 @@ MultiWorkspace* multi_workspace(blest_graph* g, void* stream, blest_status* st) 
   const size_t n = g->n;
   hipError_t e = ws->vis.alloc(16 * n);
   if (e == hipSuccess) e = ws->front.alloc(8 * n);
+  if (e == hipSuccess) e = ws->touched.alloc((size_t)std::max<uint32_t>(g->bvss.num_sets, 1) * g->bvss.sigma);
   if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 2 * std::max<size_t>(g->bvss.num_vss, 1));
   if (e == hipSuccess) e = ws->ctrl.alloc(sizeof(uint32_t) * kCtrlWords);
   if (e == hipSuccess) e = hipMemset(ws->ctrl.p, 0, sizeof(uint32_t) * kCtrlWords);
@@ -493,6 +494,7 @@ blest_status blest_bfs_multi(blest_handle h, const uint32_t* sources, uint32_t k
     p.orig_id = h->identity ? nullptr : h->d_orig_id.as<uint32_t>();
     p.vis = ws->vis.as<unsigned long long>();
     p.front = ws->front.as<unsigned long long>();
+    p.touched = ws->touched.as<uint8_t>();
     p.queue = ws->queue.as<uint32_t>();
     p.ctrl = ws->ctrl.as<uint32_t>();
     p.levels = levels_out;
@@ -703,7 +705,8 @@ blest_status blest_footprint(blest_handle h, uint32_t k, uint64_t* bytes) {
   if (k == 1)
     ws = 4 * nw * 4 + 32 * nw + q + kCtrlWords * 4;
   else
-    ws = 3ull * h->n * 8 + q + kCtrlWords * 4;  // 64-bit frontier/visited rows
+    ws = 3ull * h->n * 8 + (uint64_t)h->bvss.num_sets * h->bvss.sigma + q +
+         kCtrlWords * 4;  // 64-bit frontier/visited rows, touched bytes
   *bytes = ws + (uint64_t)k * h->n * 4;
   return BLEST_OK;
 }

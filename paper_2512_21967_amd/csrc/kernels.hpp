@@ -71,6 +71,7 @@ struct MultiParams {
   const uint32_t* orig_id;        // nullptr = identity
   unsigned long long* vis;        // 2 * n: (current, next) per vertex
   unsigned long long* front;      // n
+  uint8_t* touched;               // num_sets * sigma bytes: vertex got new bits this level
   uint32_t* queue;                // 2 * qcap
   uint32_t* ctrl;                 // kCtrlWords
   int32_t* levels;                // k * n, original IDs, row j for source j

@@ -7,9 +7,10 @@
 // That OR is the exact Boolean form of the popcount threshold of Eq. (1) taken
 // over k columns at once.  The update is lazy (Algorithm 3): Stage 1 ORs the new
 // bits into u's next-visited word with one 64-bit atomic (skipped when nothing is
-// new); Stage 2 sweeps the vertices, sets the levels of every (source, vertex)
-// pair that changed, rebuilds the frontier words and queues the VSSs of every
-// slice set with a changed vertex.
+// new); Stage 2 visits the vertices that changed (tracked by a state byte per
+// vertex, or by a full sweep on dense levels), sets the levels of every (source,
+// vertex) pair that changed, rebuilds the frontier words and queues the VSSs of
+// every slice set with a changed vertex.
 //
 // With sigma = 8 the B tile is 8 x 64 bits and a mask has about one set bit on
 // skewed graphs, so the product is done with VALU selects and ORs; an int8 matrix
@@ -22,10 +23,13 @@
 namespace blest {
 namespace {
 
+// A level is swept densely when its queue holds at least 1/kDenseFrac of the VSSs.
+constexpr uint64_t kDenseFrac = 16;
+
 __device__ __forceinline__ uint32_t morig(const MultiParams& p, uint32_t u) { return p.orig_id ? p.orig_id[u] : u; }
 
 template <typename MT, int SLOTS>
-__device__ __forceinline__ void multi_stage1(const MultiParams& p, const uint32_t* qc, uint32_t len) {
+__device__ __forceinline__ void multi_stage1(const MultiParams& p, const uint32_t* qc, uint32_t len, bool mark) {
   constexpr int SIG = 8 * sizeof(MT);
   const MT* masks = static_cast<const MT*>(p.masks);
   const uint32_t lane = lane_id();
@@ -72,42 +76,111 @@ __device__ __forceinline__ void multi_stage1(const MultiParams& p, const uint32_
 #pragma unroll
       for (int r = 0; r < SLOTS; ++r) {
         const uint64_t fresh = acc[r] & ~cv[r].x & ~cv[r].y;
-        if (fresh) atomicOr(p.vis + 2 * (uint64_t)u[r] + 1, (unsigned long long)fresh);
+        if (fresh) {
+          atomicOr(p.vis + 2 * (uint64_t)u[r] + 1, (unsigned long long)fresh);
+          // Every level starts with next == current for all vertices, so the first
+          // OR that changes u's next word was issued by a thread that read them
+          // equal: only such threads need to mark u touched.
+          if (mark && cv[r].y == cv[r].x) p.touched[u[r]] = 1;
+        }
       }
     }
   }
 }
 
+// Stage 2, driven by one state byte per vertex: 1 = Stage 1 gave the vertex new
+// bits this level (stored next to the OR), 2 = the vertex is on the current
+// frontier.  Each thread reads the bytes of four consecutive vertices as one
+// word; wavefronts whose words are all zero do nothing else.  A touched vertex
+// loads its visited pair, writes its levels and frontier word and moves to state
+// 2; a state-2 vertex that was not touched again gets a zero frontier word and
+// state 0.  So the frontier words are exactly the per-level differences, as if
+// every vertex were swept, while vertices in neither state cost one byte read.
+// On high-diameter graphs (small frontiers, thousands of levels) this avoids
+// touching every vertex's 24 bytes of visited and frontier words at every level.
+// A slice set (sigma / 4 consecutive lanes) with a touched vertex queues its VSS
+// range.  Levels flagged dense (a large queue, so most vertices change) skip the
+// byte stores in Stage 1 and sweep every vertex here instead, rewriting all
+// state bytes.
 template <int SIG>
-__device__ __forceinline__ void multi_stage2(const MultiParams& p, uint32_t* qn, uint32_t* qlen, int32_t level) {
+__device__ __forceinline__ void multi_stage2(const MultiParams& p, uint32_t* qn, uint32_t* qlen, int32_t level,
+                                             bool dense) {
+  constexpr uint32_t L = SIG / 4;  // lanes per slice set
+  static_assert(L >= 2 && L <= kWave, "slice set must span whole lanes of one wavefront");
   __shared__ uint32_t s_wave[kMaxWaves];
   __shared__ uint32_t s_base;
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
-  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < p.n; b0 += gridDim.x * blockDim.x) {
-    const uint32_t u = b0 + threadIdx.x;
-    uint64_t diff = 0;
-    if (u < p.n) {
-      const ulonglong2 cv = reinterpret_cast<const ulonglong2*>(p.vis)[u];
-      diff = cv.y & ~cv.x;
-      p.front[u] = diff;
-      if (diff) {
-        p.vis[2 * (uint64_t)u] = cv.y;
-        const uint32_t uo = morig(p, u);
-        uint64_t d = diff;
-        while (d) {
-          const uint32_t j = __ffsll((unsigned long long)d) - 1;
-          p.levels[(uint64_t)j * p.n + uo] = level;
-          d &= d - 1;
+  const uint32_t nq = p.num_sets * L;
+  uint32_t* tq = reinterpret_cast<uint32_t*>(p.touched);
+  const ulonglong2* vis2 = reinterpret_cast<const ulonglong2*>(p.vis);
+  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < nq; b0 += gridDim.x * blockDim.x) {
+    const uint32_t q = b0 + threadIdx.x;
+    // The wavefront's 64 words cover 256 consecutive vertices; in round r lane l
+    // takes vertex r * 64 + l, so that level and frontier stores of a round are
+    // contiguous across lanes.
+    const uint32_t base = 4 * (q - lane);
+    uint32_t hit;  // per word: nonzero iff one of its four vertices changed
+    if (dense) {
+      // full sweep: every vertex, state bytes rewritten (Stage 1 stored none)
+      uint64_t m[4];
+#pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t u = base + r * kWave + lane;
+        uint64_t diff = 0;
+        if (u < p.n) {
+          const ulonglong2 cv = vis2[u];
+          diff = cv.y & ~cv.x;
+          p.front[u] = diff;
+          p.touched[u] = diff ? 2 : 0;
+          if (diff) {
+            p.vis[2 * (uint64_t)u] = cv.y;
+            const uint32_t uo = morig(p, u);
+            uint64_t d = diff;
+            while (d) {
+              const uint32_t jj = __ffsll((unsigned long long)d) - 1;
+              p.levels[(uint64_t)jj * p.n + uo] = level;
+              d &= d - 1;
+            }
+          }
         }
+        m[r] = __ballot(diff != 0);
+      }
+      const uint32_t r = lane >> 4;
+      const uint64_t mr = r == 0 ? m[0] : r == 1 ? m[1] : r == 2 ? m[2] : m[3];
+      hit = (uint32_t)(mr >> ((4 * lane) & 63u)) & 0xFu;
+    } else {
+      const uint32_t tw = q < nq ? tq[q] : 0u;
+      hit = tw & 0x01010101u;  // touched this level
+      if (__ballot(tw != 0)) {
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+          const uint32_t w = (uint32_t)__shfl((int)tw, (int)(r * 16 + (lane >> 2)));
+          const uint32_t b = (w >> (8 * (lane & 3u))) & 0xFFu;
+          const uint32_t u = base + r * kWave + lane;
+          if (b == 2) p.front[u] = 0;  // left the frontier
+          if (b & 1u) {
+            const ulonglong2 cv = vis2[u];
+            const uint64_t diff = cv.y & ~cv.x;
+            p.front[u] = diff;
+            p.vis[2 * (uint64_t)u] = cv.y;
+            const uint32_t uo = morig(p, u);
+            uint64_t d = diff;
+            while (d) {
+              const uint32_t jj = __ffsll((unsigned long long)d) - 1;
+              p.levels[(uint64_t)jj * p.n + uo] = level;
+              d &= d - 1;
+            }
+          }
+        }
+        if (tw) tq[q] = hit << 1;
       }
     }
-    // a slice set is active iff one of its sigma consecutive vertices changed
-    const uint64_t changed = __ballot(diff != 0);
+    const uint64_t act = __ballot(hit != 0);
     uint32_t cnt = 0, vb[1] = {0}, vn[1] = {0};
-    const bool leader = (lane % SIG) == 0 && u < p.n;
-    if (leader && ((changed >> lane) & (SIG == 64 ? ~0ull : ((1ull << SIG) - 1))) != 0) {
-      const uint32_t ss = u / SIG;
+    constexpr uint64_t kSetLanes = L == 64 ? ~0ull : ((1ull << L) - 1);
+    if ((lane % L) == 0 && q < nq && ((act >> lane) & kSetLanes)) {
+      const uint32_t ss = q / L;
       vb[0] = p.real_ptrs[ss];
       vn[0] = cnt = p.real_ptrs[ss + 1] - vb[0];
     }
@@ -150,7 +223,9 @@ __global__ __launch_bounds__(1024) void bfs_multi_persistent(MultiParams p) {
     p.vis[2 * (uint64_t)u] = b;
     p.vis[2 * (uint64_t)u + 1] = b;
     p.front[u] = b;
+    p.touched[u] = b ? 2 : 0;  // the sources make up the level-0 frontier
   }
+  for (uint32_t u = p.n + tid; u < p.num_sets * SIG; u += nt) p.touched[u] = 0;
   // initial queue: the VSS ranges of the sources' distinct slice sets
   {
     uint32_t off = 0;
@@ -173,9 +248,12 @@ __global__ __launch_bounds__(1024) void bfs_multi_persistent(MultiParams p) {
     const uint32_t len = ld_relaxed(qlen + ((level - 1) % 3) * kLine);
     uint32_t* qnext_len = qlen + (level % 3) * kLine;
     if (tid == 0) __hip_atomic_store(qlen + ((level + 1) % 3) * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    multi_stage1<MT, SLOTS>(p, qc, len);
+    // levels that queue many VSSs touch most vertices: there the per-vertex
+    // state bytes cost more than sweeping every vertex
+    const bool dense = (uint64_t)len * kDenseFrac >= p.num_vss;
+    multi_stage1<MT, SLOTS>(p, qc, len, !dense);
     grid_barrier(ctrl);
-    multi_stage2<SIG>(p, qn, qnext_len, level);
+    multi_stage2<SIG>(p, qn, qnext_len, level, dense);
     grid_barrier(ctrl);
     if (ld_relaxed(qnext_len) == 0) break;
   }
