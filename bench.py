@@ -177,6 +177,69 @@ def run_single(args):
 
 
 # ---------------------------------------------------------------------------
+# ordering window sweep (compression quality against BFS time)
+# ---------------------------------------------------------------------------
+
+def run_wsweep(args):
+    """R-MAT S22 under Algorithm 1 with windows w = 2^3 .. 2^18 (the analogue of the
+    paper's window study, Figure 3), plus the graph with no reordering in permuted
+    labels and in the generator's own labels (the natural-order check).  Each entry
+    reports compression, VSS count, ordering time and the time of the headline's 64
+    single-source BFSs."""
+    import numpy as np
+    import torch
+    import inputs
+    import paper_2512_21967_amd as blest
+
+    permuted = inputs.rmat_workload(22, 16, seed=1, permute_seed=2)
+    natural = inputs.rmat_workload(22, 16, seed=1)
+    sources = inputs.sources(permuted, seed=3, k=64)
+    runs = [("permuted", "none", 1 << 16), ("generator", "none", 1 << 16)] + \
+           [("permuted", "compression", 1 << e) for e in (3, 6, 9, 12, 14, 16, 18)]
+    stream = torch.cuda.current_stream()
+    out = torch.empty(permuted.n, dtype=torch.int32, device="cuda")
+    # generator vertex v is permuted vertex perm[v]: map the sources back
+    perm = inputs.permutation(permuted.n, 2)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(permuted.n, dtype=np.uint32)
+    degs = {"permuted": permuted.degrees(), "generator": natural.degrees()}
+    sweep, headline, total_ms = [], None, 0.0
+    for labels, reorder, w in runs:
+        gr = permuted if labels == "permuted" else natural
+        src = sources if labels == "permuted" else inv[sources]
+        t0 = time.time()
+        g = blest.Graph(gr, reorder=reorder, window=w, update="lazy", device=0)
+        st = g.stats()
+        build_s = time.time() - t0
+        edges = 0.0
+        for s in src:
+            lv = g.bfs(int(s), levels=out, stream=stream).cpu().numpy()
+            edges += degs[labels][lv >= 0].sum() / 2.0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            for s in src:
+                g.bfs(int(s), levels=out, stream=stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        g.close()
+        rec = {"labels": labels, "reorder": reorder, "window": w if reorder == "compression" else None,
+               "compression": round(st["compression"], 4), "num_vss": st["num_vss"],
+               "reorder_s": round(st["reorder_seconds"], 2), "build_s": round(build_s, 2),
+               "ms_per_bfs": round(wall * 1000 / (args.steps * len(src)), 4),
+               "gteps": round(edges * args.steps / wall / 1e9, 3)}
+        log(f"[bench] {rec}")
+        sweep.append(rec)
+        total_ms += wall * 1000 / args.steps
+        if labels == "permuted" and reorder == "compression" and w == 1 << 16:
+            headline = rec
+    config = {"workload": "R-MAT scale 22 ef 16, 64 sources, lazy; Algorithm 1 window sweep w = 2^3..2^18 "
+                          "and no reordering (permuted and generator labels); value at w = 65536",
+              "n": permuted.n, "arcs": int(permuted.nnz), "sources": len(sources)}
+    line(headline["gteps"], args, total_ms / len(runs), "u32", config, None, None, {"sweep": sweep})
+
+
+# ---------------------------------------------------------------------------
 # k-source batch
 # ---------------------------------------------------------------------------
 
@@ -373,7 +436,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22",
-                    choices=["rmat22", "rmat16", "grid4096", "rmat20x64", "many256", "serve"])
+                    choices=["rmat22", "rmat16", "grid4096", "rmat20x64", "many256", "serve", "wsweep"])
     ap.add_argument("--update", default="auto", choices=["auto", "eager", "lazy"])
     ap.add_argument("--ranges", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -392,6 +455,8 @@ def main():
         run_many(args)
     elif args.workload == "serve":
         run_serve(args)
+    elif args.workload == "wsweep":
+        run_wsweep(args)
     else:
         run_single(args)
 

@@ -201,14 +201,30 @@ enum {
 blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t capacity_bytes,
                           uint64_t* size_bytes);
 
+/* Per-source statistics of a DEVICE level array (k rows of n int32, row j the
+ * levels from source j, -1 = unreached; the layout blest_bfs_multi writes), for
+ * the multi-source analytics the stacked frontiers of Section 2 serve (centrality,
+ * diameter).  Writes to DEVICE arrays of k entries: reached[j] = number of
+ * levels >= 0, total[j] = their sum, ecc[j] = their maximum (-1 for an empty
+ * row), far[j] = the smallest vertex at level ecc[j] (0xFFFFFFFF for an empty
+ * row) and closeness[j] = (reached[j] - 1) / total[j] in double precision (0 when
+ * total[j] = 0).  Runs on `stream` (hipStream_t, NULL = default) of `device`
+ * without host synchronisation and allocates nothing; the outputs must not alias
+ * `levels`.  k = 0 does nothing.  Errors: INVALID_ARGUMENT (k > 65535 or a null
+ * pointer), NO_DEVICE, DEVICE (launch failure). */
+blest_status blest_level_stats(int32_t device, const int32_t* levels, uint32_t k, uint32_t n, uint64_t* reached,
+                               uint64_t* total, int32_t* ecc, uint32_t* far, double* closeness, void* stream);
+
 /* Algorithmic device bytes of one BFS call whose result is `levels` (HOST int32,
  * k rows of n in original IDs, k = 1 for blest_bfs, 1..64 for blest_bfs_multi):
  * for every iteration l and every slice set holding a vertex of level l - 1 in any
  * row, its unpadded slices (4-byte row ID + sigma/8-byte mask), its frontier (the
  * sigma-bit chunk, or sigma 64-bit words when k > 1) and 8 bytes per VSS (queue
  * entry + VSS metadata); plus, for k = 1, the lazy scheme's per-level sweep of the
- * two n-bit visited bitmaps and the 4n-byte level initialisation; for k > 1 a
- * 24n-byte vertex sweep per level, the 4kn-byte initialisation and 4 bytes per
+ * two n-bit visited bitmaps and the 4n-byte level initialisation; for k > 1, per
+ * iteration, a 25n-byte vertex sweep when the queue holds at least 1/16 of the
+ * VSSs, else n state bytes plus 26 bytes per vertex changed in the iteration and 8
+ * per vertex leaving the frontier; the 4kn-byte initialisation and 4 bytes per
  * reached (source, vertex) pair.  Lets a benchmark turn a measured time into GB/s.
  * Errors: INVALID_ARGUMENT. */
 blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k, uint64_t* bytes);

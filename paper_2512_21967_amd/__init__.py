@@ -27,7 +27,7 @@ EXPORT = {"new_id": (0, np.uint32), "real_ptrs": (1, np.uint32), "virtual_to_rea
           "vss_begin": (3, np.uint32), "row_ids": (4, np.uint32), "masks": (5, np.uint8),
           "vss_range": (6, np.uint8), "order_id": (7, np.uint32)}
 EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_bfs_multi", "blest_bfs_many",
-                    "blest_batch_create", "blest_batch_run", "blest_batch_destroy", "blest_configure", "blest_stats", "blest_footprint", "blest_export", "blest_model_bytes", "blest_destroy",
+                    "blest_batch_create", "blest_batch_run", "blest_batch_destroy", "blest_configure", "blest_stats", "blest_footprint", "blest_export", "blest_model_bytes", "blest_level_stats", "blest_destroy",
                     "blest_status_string")
 
 
@@ -98,6 +98,8 @@ def lib():
     L.blest_export.restype = ctypes.c_int
     L.blest_model_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), u32, ctypes.POINTER(u64)]
     L.blest_model_bytes.restype = ctypes.c_int
+    L.blest_level_stats.argtypes = [i32, vp, u32, u32, vp, vp, vp, vp, vp, vp]
+    L.blest_level_stats.restype = ctypes.c_int
     L.blest_destroy.argtypes = [vp]
     L.blest_destroy.restype = None
     L.blest_status_string.argtypes = [ctypes.c_int]
@@ -214,6 +216,47 @@ class Graph:
                                                         ctypes.c_void_p(levels.data_ptr()), _stream_ptr(stream)))
         return levels
 
+    # -- multi-source analytics on the k-source BFS ----------------------------
+    def source_stats(self, sources, stream=None) -> dict:
+        """Reached count, level sum, eccentricity, smallest farthest vertex and
+        closeness (reached - 1) / sum of every source, from k-source BFS calls of
+        up to 64 sources each; numpy arrays."""
+        src = np.ascontiguousarray(sources, dtype=np.uint32)
+        parts = []
+        for i in range(0, src.size, 64):
+            st = level_stats(self.bfs_multi(src[i:i + 64], stream=stream), stream=stream)
+            parts.append({k: v.cpu().numpy() for k, v in st.items()})
+        return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]} if parts else {}
+
+    def closeness(self, sources, stream=None) -> np.ndarray:
+        return self.source_stats(sources, stream)["closeness"]
+
+    def diameter_bounds(self, sources, sweeps=2, undirected=True, stream=None):
+        """(lower, upper, sweep_sources) for the largest finite distance D: each
+        sweep is one k-source BFS; lower = the largest eccentricity seen, the next
+        sweep starting from the distinct farthest vertices of this one (at most 64,
+        in first-seen order); upper = 2 * min eccentricity over rows that reached
+        every vertex (the graph is then connected), for undirected graphs, else
+        None."""
+        src = [int(s) for s in sources][:64]
+        lower, upper, used = -1, None, []
+        for _ in range(max(1, sweeps)):
+            st = self.source_stats(src, stream)
+            used.append(list(src))
+            lower = max(lower, int(st["ecc"].max()))
+            if undirected:
+                full = st["reached"] == self.n
+                if full.any():
+                    u = 2 * int(st["ecc"][full].min())
+                    upper = u if upper is None else min(upper, u)
+            nxt = []
+            for f in st["far"]:
+                f = int(f)
+                if f != 0xFFFFFFFF and f not in nxt:
+                    nxt.append(f)
+            src = nxt[:64]
+        return lower, upper, used
+
     def configure(self, update="auto", block=0, blocks_per_cu=0, group=0):
         """Changes launch settings (update scheme, workgroup shape, group depth)."""
         _check("blest_configure", lib().blest_configure(self.handle, UPDATE[update], block, blocks_per_cu, group))
@@ -251,6 +294,32 @@ class Graph:
                                                             lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                                             lv.size // self.n, ctypes.byref(b)))
         return int(b.value)
+
+
+def level_stats(levels, stream=None) -> dict:
+    """Per-row statistics of an int32 CUDA level tensor [k, n] (or [n]) computed on
+    the device (``blest_level_stats``): reached (int64), total (int64, sum of the
+    finite levels), ecc (int32, -1 for an empty row), far (int64, smallest vertex at
+    level ecc, 0xFFFFFFFF for an empty row) and closeness (float64), as CUDA tensors
+    of k entries."""
+    import torch
+    if not isinstance(levels, torch.Tensor) or levels.dtype != torch.int32 or not levels.is_cuda \
+            or not levels.is_contiguous():
+        raise TypeError("levels must be a contiguous int32 CUDA tensor")
+    lv = levels if levels.dim() == 2 else levels.view(1, -1)
+    k, n = int(lv.shape[0]), int(lv.shape[1])
+    dev = lv.device
+    reached = torch.empty(k, dtype=torch.int64, device=dev)
+    total = torch.empty(k, dtype=torch.int64, device=dev)
+    ecc = torch.empty(k, dtype=torch.int32, device=dev)
+    far = torch.empty(k, dtype=torch.int32, device=dev)
+    close = torch.empty(k, dtype=torch.float64, device=dev)
+    _check("blest_level_stats", lib().blest_level_stats(
+        dev.index if dev.index is not None else torch.cuda.current_device(), ctypes.c_void_p(lv.data_ptr()), k, n,
+        ctypes.c_void_p(reached.data_ptr()), ctypes.c_void_p(total.data_ptr()), ctypes.c_void_p(ecc.data_ptr()),
+        ctypes.c_void_p(far.data_ptr()), ctypes.c_void_p(close.data_ptr()), _stream_ptr(stream)))
+    return {"reached": reached, "total": total, "ecc": ecc, "far": far.to(torch.int64) & 0xFFFFFFFF,
+            "closeness": close}
 
 
 def bfs_many(graphs, sources, outs=None, stream=None):

@@ -732,6 +732,24 @@ blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t cap
   return BLEST_OK;
 }
 
+blest_status blest_level_stats(int32_t device, const int32_t* levels, uint32_t k, uint32_t n, uint64_t* reached,
+                               uint64_t* total, int32_t* ecc, uint32_t* far, double* closeness, void* stream) {
+  if (k == 0) return BLEST_OK;
+  if (k > 65535 || (n && !levels) || !reached || !total || !ecc || !far || !closeness)
+    return BLEST_ERR_INVALID_ARGUMENT;
+  int count = 0;
+  if (device < 0 || hipGetDeviceCount(&count) != hipSuccess || device >= count) return BLEST_ERR_NO_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return BLEST_ERR_DEVICE;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+    return BLEST_ERR_DEVICE;
+  static_assert(sizeof(unsigned long long) == sizeof(uint64_t), "64-bit counters");
+  const hipError_t e = launch_level_stats(levels, k, n, reinterpret_cast<unsigned long long*>(reached),
+                                          reinterpret_cast<unsigned long long*>(total), ecc, far, closeness,
+                                          (uint32_t)cus, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BLEST_OK : BLEST_ERR_DEVICE;
+}
+
 blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k, uint64_t* bytes) {
   if (!h || !levels || !bytes || k == 0 || k > 64) return BLEST_ERR_INVALID_ARGUMENT;
   const Bvss& b = h->bvss;
@@ -785,8 +803,43 @@ blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k
     if (h->lazy) total += iters * 2ull * ((n + 7) / 8);  // Stage 2 reads both visited bitmaps
     total += 4ull * n;                                      // level initialisation
   } else {
-    total += iters * 24ull * n;                            // vertex sweep: visited pair + frontier word
-    total += 4ull * k * n + 4ull * reached;                // level initialisation + level writes
+    // Stage 2 per iteration i: a dense iteration (queue >= 1/16 of the VSSs) sweeps
+    // every vertex (visited pair, frontier word, state byte: 25 B); a sparse one
+    // reads the n state bytes and moves 24 B + 2 state bytes per vertex that
+    // changed at level i (one store in Stage 1, one in Stage 2) and zeroes the
+    // frontier word of each vertex of level i - 1.  A vertex changes at level l iff
+    // some row has it at level l; queues hold the VSSs of sets with such a vertex.
+    std::vector<uint64_t> changed(iters + 1, 0), queued(iters + 2, 0);
+    std::vector<int32_t> lv;
+    std::vector<uint8_t> set_has;
+    for (uint32_t s = 0; s < b.num_sets; ++s) {
+      const uint32_t v0 = s * b.sigma, v1 = std::min<uint32_t>(n, v0 + b.sigma);
+      set_has.assign(iters + 1, 0);
+      for (uint32_t v = v0; v < v1; ++v) {
+        const uint32_t vo = h->orig_id_of(v);
+        lv.clear();
+        for (uint32_t j = 0; j < k; ++j) {
+          const int32_t l = levels[(uint64_t)j * n + vo];
+          if (l >= 0) lv.push_back(l);
+        }
+        std::sort(lv.begin(), lv.end());
+        lv.erase(std::unique(lv.begin(), lv.end()), lv.end());
+        for (const int32_t l : lv) {
+          ++changed[l];
+          set_has[l] = 1;
+        }
+      }
+      const uint64_t nv = b.real_ptrs[s + 1] - b.real_ptrs[s];
+      for (uint64_t l = 0; l < iters; ++l)
+        if (set_has[l]) queued[l + 1] += nv;
+    }
+    for (uint64_t i = 1; i <= iters; ++i) {
+      if (queued[i] * 16 >= b.num_vss)
+        total += 25ull * n;
+      else
+        total += n + 26ull * (i < iters ? changed[i] : 0) + 8ull * changed[i - 1];
+    }
+    total += 4ull * k * n + n + 4ull * reached;            // level, visited and state initialisation + level writes
   }
   *bytes = total;
   return BLEST_OK;

@@ -106,6 +106,11 @@ hipError_t launch_bfs_many(const ManyItem* items, uint32_t g, uint32_t max_n, ui
 
 // Parents post-pass: parent[v] = smallest original ID among the in-neighbours of v
 // on level level[v] - 1.  Ordinary launches on `stream`.
+// Per-row reached count, level sum, eccentricity, smallest farthest vertex and
+// closeness of a k x n level array (k <= 65535).
+hipError_t launch_level_stats(const int32_t* levels, uint32_t k, uint32_t n, unsigned long long* reached,
+                              unsigned long long* total, int32_t* ecc, uint32_t* far, double* closeness,
+                              uint32_t num_cus, hipStream_t stream);
 hipError_t launch_parents(const BfsParams& p, uint32_t sigma, const int32_t* levels, int32_t* parents,
                           hipStream_t stream);
 
