@@ -45,7 +45,7 @@ def traffic_from_profiles(key):
         return None
     with open(path) as f:
         rec = json.load(f).get(key)
-    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash(rec.get("kernel_sources")):
         return None
     return rec.get("bytes_per_launch")
 
@@ -283,13 +283,25 @@ def run_multi(args):
     torch.cuda.synchronize()
     seq = time.perf_counter() - t1
     seq_gteps = row_edges.sum() / seq / 1e9
+    # the analytics reduction over the launch's 64 x n levels (blest_level_stats)
+    for _ in range(2):
+        blest.level_stats(out, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        blest.level_stats(out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stats_ms = e0.elapsed_time(e1) / 5
     roof = roofline(model, ms.mean() / 1000.0, "rmat20x64/multi")
     log(f"[bench] k=64 launch: {ms.mean():.3f} ms, {gteps:.1f} GTEPS; 64 sequential single-source: "
         f"{seq * 1000:.2f} ms, {seq_gteps:.1f} GTEPS ({gteps / seq_gteps:.1f}x); {roof['achieved']:.0f} GB/s")
     cpu = None if args.no_cpu_baseline else oracle_baseline([(gr, s) for s in srcs], row_edges, args.cpu_seconds, args.cpu_threads)
     config = {"workload": "R-MAT scale 20 ef 16, generator labels, 64 distinct sources in one k-source launch",
               "n": gr.n, "arcs": int(gr.nnz), "sources": 64, "sequential_single_source_gteps": round(seq_gteps, 3),
-              "speedup_vs_sequential": round(gteps / seq_gteps, 2), "ms_per_launch_mean": round(float(ms.mean()), 4)}
+              "speedup_vs_sequential": round(gteps / seq_gteps, 2), "ms_per_launch_mean": round(float(ms.mean()), 4),
+              "level_stats_ms": round(stats_ms, 4),
+              "level_stats_one_pass_gbs": round(4.0 * 64 * gr.n / (stats_ms / 1000.0) / 1e9, 1)}
     line(gteps, args, wall * 1000 / args.steps, "u64", config, roof, cpu)
 
 

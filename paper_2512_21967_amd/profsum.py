@@ -10,8 +10,9 @@
       one `--pmc WRITE_SIZE` run, each scaled by what the same counter read for the
       plain device copy of --copy-bytes (read once, written once) that the profiled
       command ran after its timed region.  Merges the record into
-      profiles/traffic.json under --key, stamped with the hash of the kernel sources
-      so that a later kernel change voids it.
+      profiles/traffic.json under --key, stamped with the hash of the csrc files the
+      kernel is built from (--sources; by default the single-source kernel's), so
+      that a later change to any of them voids it.
 """
 from __future__ import annotations
 
@@ -26,12 +27,23 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def kernel_source_hash():
+CSRC = os.path.join(ROOT, "paper_2512_21967_amd", "csrc")
+# Sources that build the single-source kernel and everything it reads or is
+# launched with (host-side layout, options, launch shape); the other kernels live
+# in translation units of their own and cannot change its code or traffic.
+SINGLE_SOURCE_FILES = ("capi.cpp", "device_common.hpp", "host.cpp", "internal.hpp", "kernels.hip", "kernels.hpp")
+
+
+def kernel_source_hash(files=None):
+    """Hash of the named csrc files (all of them when files is None)."""
+    if files is None:
+        paths = [f for f in sorted(glob.glob(os.path.join(CSRC, "*"))) if f.endswith((".hip", ".hpp", ".cpp"))]
+    else:
+        paths = [os.path.join(CSRC, f) for f in sorted(files)]
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2512_21967_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".hpp", ".cpp")):
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    for f in paths:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -99,7 +111,8 @@ def traffic(args):
             db = json.load(f)
     db[args.key] = {"bytes_per_launch": round(fetch + write), "fetch_bytes_per_launch": round(fetch),
                     "write_bytes_per_launch": round(write), "fetch_scale": round(ff, 4), "write_scale": round(fw, 4),
-                    "dispatches": [nf, nw], "kernel": args.kernel, "kernel_source_hash": kernel_source_hash(),
+                    "dispatches": [nf, nw], "kernel": args.kernel, "kernel_sources": sorted(args.sources),
+                    "kernel_source_hash": kernel_source_hash(args.sources),
                     "commands": [args.cmd_fetch, args.cmd_write]}
     with open(path, "w") as f:
         json.dump(db, f, indent=1, sort_keys=True)
@@ -121,6 +134,8 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=float, default=float(256 << 20))
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
+    t.add_argument("--sources", nargs="+", default=list(SINGLE_SOURCE_FILES),
+                   help="csrc files whose hash stamps the record (default: the single-source kernel's)")
     args = ap.parse_args(argv)
     stats(args) if args.what == "stats" else traffic(args)
 

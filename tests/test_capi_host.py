@@ -345,3 +345,14 @@ def test_footprint_and_model_bytes():
     lv[:] = 0
     b_all = g.model_bytes(lv)
     assert 4 * gr.n < b_one < b_all
+
+
+def test_traffic_record_hash_scope():
+    """The traffic record's hash covers the files that build the single-source
+    kernel; every one of them exists, and the hash changes with their content."""
+    from paper_2512_21967_amd import profsum
+    for f in profsum.SINGLE_SOURCE_FILES:
+        assert os.path.exists(os.path.join(profsum.CSRC, f)), f
+    a = profsum.kernel_source_hash(profsum.SINGLE_SOURCE_FILES)
+    assert a == profsum.kernel_source_hash(list(reversed(profsum.SINGLE_SOURCE_FILES)))
+    assert a != profsum.kernel_source_hash(profsum.SINGLE_SOURCE_FILES[:-1])

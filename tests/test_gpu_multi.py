@@ -126,3 +126,31 @@ def test_high_diameter_grid(slots):
     g = blest.Graph(gr, reorder="bandwidth", slots=slots)
     srcs = inputs.sources(gr, seed=9, k=40)
     np.testing.assert_array_equal(run_multi(g, srcs), oracle.bfs_multi(gr, srcs))
+
+
+def _csr_arcs(gr, offset):
+    rows = np.repeat(np.arange(gr.n, dtype=np.int64), np.diff(gr.row_ptr.astype(np.int64)))
+    return rows + offset, gr.col.astype(np.int64) + offset
+
+
+def test_levels_switch_between_dense_and_sparse():
+    """Two R-MAT blobs joined by a 3,000-vertex path: the blobs' middle levels queue
+    many VSSs (full vertex sweep), the path's levels queue one or two (per-vertex
+    state bytes), and the k-source call crosses between the two more than once,
+    with sources in both blobs and on the path."""
+    a = inputs.rmat(12, 8, seed=21)
+    b = inputs.rmat(12, 8, seed=22)
+    plen = 3000
+    base_p, base_b = a.n, a.n + plen
+    sa, da = _csr_arcs(a, 0)
+    sb, db = _csr_arcs(b, base_b)
+    # the path runs from blob a's vertex 0 through base_p .. base_b - 1 into blob b's
+    # vertex 0 (R-MAT's vertex 0 has the largest expected degree)
+    chain = np.concatenate([[0], np.arange(base_p, base_b), [base_b]]).astype(np.int64)
+    ps, pd = chain[:-1], chain[1:]
+    n = base_b + b.n
+    gr = inputs.from_arcs(n, np.concatenate([sa, sb, ps]), np.concatenate([da, db, pd]), True)
+    srcs = np.array([0, 17, base_p + 5, base_p + plen // 2, base_b, base_b + 3, n - 1], np.uint32)
+    for reorder in ("none", "compression"):
+        g = blest.Graph(gr, reorder=reorder)
+        np.testing.assert_array_equal(run_multi(g, srcs), oracle.bfs_multi(gr, srcs), err_msg=reorder)
