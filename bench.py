@@ -270,6 +270,8 @@ def run_multi(args):
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_begin
+    if args.calibrate_copy:
+        copy_calibration()
     ms = np.array([a.elapsed_time(b) for a, b in ev])
     gteps = row_edges.sum() * args.steps / wall / 1e9
     # the comparison: the same 64 sources as 64 single-source launches
