@@ -56,39 +56,26 @@ def num_slice_sets(n: int, sigma: int) -> int:
     return -(-n // sigma)
 
 
-def vss_partition(set_id, row, mask, n_sets: int, tau: int, row_block: int | None = None):
-    """Splits the (set, row)-sorted slices into virtual slice sets.
+def vss_partition(set_id, row, mask, n_sets: int, tau: int):
+    """Splits the (set, row)-sorted slices into virtual slice sets: the slices of
+    each set, in row order, cut into consecutive groups of tau (Section 2.1, rules 1
+    and 2), so only a set's last VSS can be short.
 
-    With row_block, a VSS additionally never spans two blocks of row_block row IDs
-    (the extra cut the MI355X layout makes so that a VSS updates one row range);
-    without it the partition is exactly the paper's.
-
-    Returns dict with realPtrs (int64[n_sets+1]), virtualToReal (int64[numVSS]),
-    blocks (the row block of each VSS, 0 without row_block) and groups: a list of
-    (row int64[], mask uint64[]) per VSS, rows ascending."""
+    Returns dict with realPtrs (int64[n_sets+1]), virtualToReal (int64[numVSS]) and
+    groups: a list of (row int64[], mask uint64[]) per VSS, rows ascending."""
     real_ptrs = [0]
     v2r = []
     groups = []
-    blocks = []
     bounds = np.searchsorted(set_id, np.arange(n_sets + 1), side="left")
     for s in range(n_sets):
         lo, hi = bounds[s], bounds[s + 1]
-        c = lo
-        while c < hi:
+        for c in range(lo, hi, tau):
             e = min(hi, c + tau)
-            blk = 0
-            if row_block:
-                blk = int(row[c]) // row_block
-                while e > c + 1 and int(row[e - 1]) // row_block != blk:
-                    e -= 1
             groups.append((row[c:e], mask[c:e]))
             v2r.append(s)
-            blocks.append(blk)
-            c = e
         real_ptrs.append(len(v2r))
     return {"realPtrs": np.array(real_ptrs, np.int64),
             "virtualToReal": np.array(v2r, np.int64),
-            "blocks": np.array(blocks, np.int64),
             "groups": groups}
 
 
