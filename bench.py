@@ -56,38 +56,66 @@ def roofline(bytes_per_launch, mean_launch_s, key):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key)}
 
 
-def oracle_baseline(graphs_and_sources, edges, seconds, threads=16):
-    """Times the oracle (single-threaded C BFS, unchanged) on a bounded prefix of
-    the work, running independent sources concurrently on `threads` host threads
-    (the C call releases the interpreter lock); stops submitting once `seconds`
-    of wall time have passed."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_leg(work, edges, seconds, threads=16, on_result=None):
+    """Times the oracle (single-threaded C BFS, unchanged).
+
+    work: [(graph, source)], edges[i]: traversed edges of work item i.  First one
+    thread runs items in order for at most ~seconds/6 (at least one item): the
+    single-thread figure.  Then `threads` host threads run independent items at
+    once (the C call releases the interpreter lock) until every item is done or
+    `seconds` of wall time have passed.  on_result(i, levels) sees every item the
+    threaded pass finished (parity checks, model bytes).  Returns the
+    cpu_baseline record."""
     import concurrent.futures as cf
     import oracle
     threads = max(1, min(threads, os.cpu_count() or 1))
-    work = list(zip(graphs_and_sources, edges))
-    oracle.bfs(work[0][0][0], int(work[0][0][1]))  # loads the library outside the timed region
+    oracle.bfs(work[0][0], int(work[0][1]))  # loads the library outside the timed region
+    e1, n1 = 0.0, 0
+    t0 = time.perf_counter()
+    while n1 < len(work) and (n1 == 0 or time.perf_counter() - t0 < seconds / 6):
+        gr, s = work[n1]
+        oracle.bfs(gr, int(s))
+        e1 += edges[n1]
+        n1 += 1
+    single = e1 / (time.perf_counter() - t0) / 1e9
     done_e, cnt = 0.0, 0
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        pending = set()
-        it = iter(work)
+        pending = {}
+        nxt = 0
         while True:
-            while len(pending) < threads and time.perf_counter() - t0 < seconds:
-                nxt = next(it, None)
-                if nxt is None:
-                    break
-                (gr, s), e = nxt
-                pending.add(ex.submit(lambda g=gr, s=s, e=e: (oracle.bfs(g, int(s)), e)[1]))
+            while len(pending) < threads and nxt < len(work) and time.perf_counter() - t0 < seconds:
+                gr, s = work[nxt]
+                pending[ex.submit(oracle.bfs, gr, int(s))] = nxt
+                nxt += 1
             if not pending:
                 break
-            fin, pending = cf.wait(pending, return_when=cf.FIRST_COMPLETED)
+            fin, _ = cf.wait(list(pending), return_when=cf.FIRST_COMPLETED)
             for f in fin:
-                done_e += f.result()
+                i = pending.pop(f)
+                lv = f.result()
+                done_e += edges[i]
                 cnt += 1
+                if on_result is not None:
+                    on_result(i, lv)
     wall = time.perf_counter() - t0
     return {"value": round(float(done_e / wall / 1e9), 5), "unit": "GTEPS", "cores": threads, "kind": "oracle",
             "sample": f"{cnt} of the {len(edges)} single-source BFSs of this workload, the single-threaded "
-                      f"FIFO-queue BFS in C run on {threads} host threads at once, {wall:.2f} s wall"}
+                      f"FIFO-queue BFS in C run on {threads} host threads at once, {wall:.2f} s wall",
+            "single_thread_gteps": round(float(single), 5),
+            "single_thread_sample": f"{n1} BFSs in order on one thread",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(), "done": cnt}
 
 
 def line(value, args, ms_per_step, dtype, config, roof, cpu, extra=None):
@@ -134,19 +162,20 @@ def run_single(args):
     st = g.stats()
     log(f"[bench] build {time.time() - t0:.1f}s: reorder {st['reorder_used']} ({st['reorder_seconds']:.1f}s), "
         f"update {st['update_used']}, compression {st['compression']:.3f}, VSS {st['num_vss']}, "
-        f"ranges {st['nranges']}, slices {st['num_slices']}, U_div {st['u_div_paper']:.0f}")
+        f"ranges {st['nranges']}, slices {st['num_slices']}, U_div {st['u_div_paper']:.0f}, "
+        f"grid {st['grid']}x{st['block']}")
     deg = gr.degrees()
     stream = torch.cuda.current_stream()
     outs = [torch.empty(gr.n, dtype=torch.int32, device="cuda") for _ in range(2)]
     edges = np.zeros(len(sources))
-    model = np.zeros(len(sources))
+    gpu_levels = [None] * len(sources)
     for w in range(max(args.warmup, 1)):
         for i, s in enumerate(sources):
             lv = g.bfs(int(s), levels=outs[i & 1], stream=stream)
             if w == 0:
                 lvh = lv.cpu().numpy()
                 edges[i] = deg[lvh >= 0].sum() / 2.0
-                model[i] = g.model_bytes(lvh)
+                gpu_levels[i] = lvh
     torch.cuda.synchronize()
     starts = [[torch.cuda.Event(enable_timing=True) for _ in sources] for _ in range(args.steps)]
     ends = [[torch.cuda.Event(enable_timing=True) for _ in sources] for _ in range(args.steps)]
@@ -163,17 +192,118 @@ def run_single(args):
         copy_calibration()
     ms = np.array([[starts[k][i].elapsed_time(ends[k][i]) for i in range(len(sources))] for k in range(args.steps)])
     gteps = edges.sum() * args.steps / wall / 1e9
-    roof = roofline(model.mean(), ms.mean() / 1000.0, f"{args.workload}/{st['update_used']}")
+    # the oracle leg: timed baseline, element-by-element parity of every GPU level
+    # array it covers, and the algorithmic bytes from the oracle's own levels
+    model = {}
+    bad = []
+
+    def check(i, want):
+        if not np.array_equal(gpu_levels[i], want):
+            bad.append(int(sources[i]))
+        model[i] = g.model_bytes(want)
+        gpu_levels[i] = None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = oracle_leg([(gr, s) for s in sources], edges, args.cpu_seconds, args.cpu_threads, check)
+        log(f"[bench] oracle: {cpu['value']} GTEPS on {cpu['cores']} threads, {cpu['single_thread_gteps']} on one "
+            f"({cpu['sample']})")
+        cpu.pop("done")
+    checked = len(model)
+    if checked < len(sources):  # no oracle levels for these: model bytes from the GPU's (identical under parity)
+        for i, lv in enumerate(gpu_levels):
+            if lv is not None:
+                model[i] = g.model_bytes(lv)
+    mb = np.array([model[i] for i in range(len(sources))], dtype=np.float64)
+    roof = roofline(mb.mean(), ms.mean() / 1000.0, f"{args.workload}/{st['update_used']}")
     log(f"[bench] {args.steps} steps: {wall * 1000 / args.steps:.2f} ms/step, {ms.mean():.3f} ms/BFS "
         f"(median {np.median(ms):.3f}), {gteps:.2f} GTEPS, {roof['achieved']:.0f} GB/s algorithmic")
-    cpu = None if args.no_cpu_baseline else oracle_baseline([(gr, s) for s in sources], edges, args.cpu_seconds, args.cpu_threads)
-    if cpu:
-        log(f"[bench] oracle: {cpu['value']} GTEPS ({cpu['sample']})")
+    parity = f"{checked - len(bad)}/{len(sources)} exact" + (f"; MISMATCH at sources {bad[:8]}" if bad else "")
+    if checked < len(sources):
+        parity += f" ({len(sources) - checked} not checked)"
     config = {"workload": desc, "n": gr.n, "arcs": int(gr.nnz), "sources": len(sources), "update": st["update_used"],
-              "sigma": st["sigma"], "tau": st["tau"], "ranges": st["nranges"],
-              "compression": round(st["compression"], 4), "ms_per_bfs_mean": round(float(ms.mean()), 4),
-              "ms_per_bfs_median": round(float(np.median(ms)), 4)}
-    line(gteps, args, wall * 1000 / args.steps, "u32", config, roof, cpu)
+              "sigma": st["sigma"], "tau": st["tau"], "ranges": st["nranges"], "grid": st["grid"],
+              "block": st["block"], "compression": round(st["compression"], 4),
+              "ms_per_bfs_mean": round(float(ms.mean()), 4), "ms_per_bfs_median": round(float(np.median(ms)), 4),
+              "model_bytes_per_bfs": int(mb.mean()), "model_bytes_from": "oracle levels" if checked else "gpu levels"}
+    extra = {"parity": parity}
+    if args.workload == "rmat22" and not args.no_batched:
+        extra["batched"] = batched_leg(args)
+    g.close()
+    line(gteps, args, wall * 1000 / args.steps, "u32", config, roof, cpu, extra)
+    if bad or ("batched" in extra and "MISMATCH" in extra["batched"]["parity"]):
+        sys.exit(1)
+
+
+def batched_leg(args):
+    """The k-source part of the metric, on its own workload (R-MAT scale 20, ef 16,
+    64 distinct sources): one k = 64 launch against 64 single-source launches of the
+    same sources on the same build, every row checked against the oracle."""
+    import numpy as np
+    import torch
+    import inputs
+    import paper_2512_21967_amd as blest
+
+    gr = inputs.rmat_workload(20, 16, seed=1)
+    srcs = inputs.sources(gr, seed=7, k=64, distinct=True)
+    g = blest.Graph(gr, reorder="none", device=0)
+    deg = gr.degrees()
+    stream = torch.cuda.current_stream()
+    out = torch.empty((64, gr.n), dtype=torch.int32, device="cuda")
+    g.bfs_multi(srcs, levels=out, stream=stream)
+    lv = out.cpu().numpy()
+    row_edges = np.array([deg[lv[j] >= 0].sum() / 2.0 for j in range(64)])
+    for _ in range(args.warmup):
+        g.bfs_multi(srcs, levels=out, stream=stream)
+    steps = max(args.steps, 5)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(steps):
+        g.bfs_multi(srcs, levels=out, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    one = torch.empty(gr.n, dtype=torch.int32, device="cuda")
+    for s in srcs[:4]:
+        g.bfs(int(s), levels=one, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        for s in srcs:
+            g.bfs(int(s), levels=one, stream=stream)
+    torch.cuda.synchronize()
+    seq = (time.perf_counter() - t1) / steps
+    gteps = row_edges.sum() * steps / wall / 1e9
+    seq_gteps = row_edges.sum() / seq / 1e9
+    ms = a.elapsed_time(b) / steps
+    # cpu_baseline leg of this workload: the oracle on the same 64 sources, whose
+    # levels also check every row of the launch and give the algorithmic bytes
+    want = np.empty_like(lv)
+    seen = []
+
+    def check(j, w):
+        want[j] = w
+        seen.append(j)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = oracle_leg([(gr, s) for s in srcs], row_edges, args.cpu_seconds, args.cpu_threads, check)
+        cpu.pop("done")
+    ok = sum(int(np.array_equal(lv[j], want[j])) for j in seen)
+    model = g.model_bytes(want if len(seen) == 64 else lv)
+    g.close()
+    log(f"[bench] batched k=64 on S20: {ms:.3f} ms/launch, {gteps:.1f} GTEPS; 64 single-source launches "
+        f"{seq * 1000:.2f} ms, {seq_gteps:.1f} GTEPS ({gteps / seq_gteps:.1f}x); parity {ok}/{len(seen)}")
+    parity = f"{ok}/64 rows exact" + ("" if ok == len(seen) else "; MISMATCH")
+    if len(seen) < 64:
+        parity += f" ({64 - len(seen)} rows not checked)"
+    return {"workload": "R-MAT scale 20 ef 16, generator labels, 64 distinct sources in one k-source launch",
+            "gteps": round(gteps, 3), "ms_per_launch": round(ms, 4), "sequential_gteps": round(seq_gteps, 3),
+            "sequential_ms": round(seq * 1000, 3), "speedup_vs_sequential": round(gteps / seq_gteps, 2),
+            "model_bytes_per_launch": int(model), "hbm_frac": round(model / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
+            "parity": parity, "cpu_baseline": cpu}
 
 
 # ---------------------------------------------------------------------------
@@ -298,13 +428,32 @@ def run_multi(args):
     roof = roofline(model, ms.mean() / 1000.0, "rmat20x64/multi")
     log(f"[bench] k=64 launch: {ms.mean():.3f} ms, {gteps:.1f} GTEPS; 64 sequential single-source: "
         f"{seq * 1000:.2f} ms, {seq_gteps:.1f} GTEPS ({gteps / seq_gteps:.1f}x); {roof['achieved']:.0f} GB/s")
-    cpu = None if args.no_cpu_baseline else oracle_baseline([(gr, s) for s in srcs], row_edges, args.cpu_seconds, args.cpu_threads)
+    want = np.empty_like(lv)
+    seen = []
+
+    def check(j, w):
+        want[j] = w
+        seen.append(j)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = oracle_leg([(gr, s) for s in srcs], row_edges, args.cpu_seconds, args.cpu_threads, check)
+        cpu.pop("done")
+        if len(seen) == 64:
+            model = g.model_bytes(want)
+            roof = roofline(model, ms.mean() / 1000.0, "rmat20x64/multi")
+    ok = sum(int(np.array_equal(lv[j], want[j])) for j in seen)
+    parity = f"{ok}/64 rows exact" + ("" if ok == len(seen) else "; MISMATCH") + \
+        ("" if len(seen) == 64 else f" ({64 - len(seen)} rows not checked)")
     config = {"workload": "R-MAT scale 20 ef 16, generator labels, 64 distinct sources in one k-source launch",
               "n": gr.n, "arcs": int(gr.nnz), "sources": 64, "sequential_single_source_gteps": round(seq_gteps, 3),
               "speedup_vs_sequential": round(gteps / seq_gteps, 2), "ms_per_launch_mean": round(float(ms.mean()), 4),
               "level_stats_ms": round(stats_ms, 4),
               "level_stats_one_pass_gbs": round(4.0 * 64 * gr.n / (stats_ms / 1000.0) / 1e9, 1)}
-    line(gteps, args, wall * 1000 / args.steps, "u64", config, roof, cpu)
+    line(gteps, args, wall * 1000 / args.steps, "u64", config, roof, cpu, {"parity": parity})
+    g.close()
+    if "MISMATCH" in parity:
+        sys.exit(1)
 
 
 # ---------------------------------------------------------------------------
@@ -367,15 +516,31 @@ def run_many(args):
     log(f"[bench] one replay: {ms.mean():.3f} ms, {gteps:.2f} GTEPS; 256 launches: {seq * 1000:.2f} ms "
         f"({edges / seq / 1e9:.2f} GTEPS)")
     cpu = None
+    got = [o.cpu().numpy() for o in batch.outs]
+    bad, seen = [], []
+
+    def check(i, w):
+        seen.append(i)
+        if not np.array_equal(got[i], w):
+            bad.append(i)
+
     if not args.no_cpu_baseline:
         ge = [gr.degrees() for gr in graphs]
-        per = [float(ge[i][batch.outs[i].cpu().numpy() >= 0].sum() / 2.0) for i in range(len(graphs))]
-        cpu = oracle_baseline(list(zip(graphs, srcs)), per, args.cpu_seconds, args.cpu_threads)
+        per = [float(ge[i][got[i] >= 0].sum() / 2.0) for i in range(len(graphs))]
+        cpu = oracle_leg(list(zip(graphs, srcs)), per, args.cpu_seconds, args.cpu_threads, check)
+        cpu.pop("done")
+    parity = f"{len(seen) - len(bad)}/{len(graphs)} graphs exact" + (f"; MISMATCH at {bad[:8]}" if bad else "") + \
+        ("" if len(seen) == len(graphs) else f" ({len(graphs) - len(seen)} not checked)")
     config = {"workload": "256 R-MAT graphs, scale U{10..16}, edge factor U{8..32}, one source each, one "
                           "graph-captured launch", "graphs": 256, "sequential_launches_ms": round(seq * 1000, 3),
               "speedup_vs_sequential": round(seq * 1000 / ms.mean(), 2),
               "ms_per_replay_mean": round(float(ms.mean()), 4)}
-    line(gteps, args, wall * 1000 / args.steps, "u32", config, roof, cpu)
+    line(gteps, args, wall * 1000 / args.steps, "u32", config, roof, cpu, {"parity": parity})
+    batch.close()
+    for h in handles:
+        h.close()
+    if bad:
+        sys.exit(1)
 
 
 # ---------------------------------------------------------------------------
@@ -458,6 +623,7 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the k-source leg of the default workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

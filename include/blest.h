@@ -75,7 +75,9 @@ typedef struct {
   int32_t device;      /* HIP device ordinal; -1 builds host-only (structure and stats) */
   uint32_t threads;    /* host threads for the build (0 = all hardware threads) */
   uint32_t block;      /* threads per workgroup of the persistent kernels, a multiple of 64 (0 = 1024) */
-  uint32_t blocks_per_cu; /* persistent workgroups per compute unit (0 = 1); block * blocks_per_cu <= 1024 */
+  uint32_t blocks_per_cu; /* persistent workgroups per compute unit (0 = 1); block * blocks_per_cu <= 2048.
+                             The grid is clamped to the workgroups a CU can really hold at once by the
+                             kernel's registers and LDS (see blest_stats_t.blocks_per_cu_own) */
   uint32_t group;      /* VSSs whose slice loads a wavefront keeps in flight: 1, 2 or 4 (0 = 2) */
   uint32_t ranges;     /* row ranges of the lazy kernel: a power of two <= 32 (0 = 1).  With R > 1
                           every VSS stays inside one range and workgroup b caches the visited bits
@@ -114,6 +116,12 @@ typedef struct {
   uint32_t lds_bytes;           /* visited bits per workgroup cached in LDS by the lazy kernel */
   uint32_t lds_chunk_words;     /* cached words per 64-word chunk of a range (64 = the whole range) */
   uint32_t hub_cpos;            /* positions per 64-word chunk that the hub sort filled first (0: none) */
+  uint32_t grid;                /* workgroups of the single-source persistent launch (0: host-only) */
+  uint32_t block;               /* threads per workgroup of the persistent launches */
+  uint32_t kernel_vgprs;        /* vector registers per lane of the single-source kernel */
+  uint32_t blocks_per_cu_runtime; /* workgroups per CU the runtime's occupancy query allows */
+  uint32_t blocks_per_cu_own;   /* workgroups per CU by the kernel's registers and LDS (gfx950 rules);
+                                   the grid uses the smaller of the two and blocks_per_cu */
 } blest_stats_t;
 
 /* Fills *opt with the defaults listed above. */
@@ -168,6 +176,72 @@ blest_status blest_batch_create(const blest_handle* hs, const uint32_t* sources,
 blest_status blest_batch_run(blest_batch_handle b, void* stream);
 void blest_batch_destroy(blest_batch_handle b);
 
+/* Continuous batching (a request loop against resident graphs).  A server owns
+ * one persistent launch on its own stream that serves BFS requests of 1..64
+ * sources on up to 4 resident graphs (handles built on one device with the same
+ * sigma and slots).  Every graph has 64 source columns; at every level boundary
+ * the launch admits waiting requests, oldest first per graph, into free columns,
+ * so a request that arrives while others run joins the running sweep instead of
+ * waiting for it, and its rows advance one level per server iteration like the
+ * others'.  A request's rows are the k-source BFS of its sources (Section 2's
+ * stacked frontiers): identical to blest_bfs_multi of the same sources alone.
+ * Requests are exchanged through a ring of 256 slots in pinned host memory; the
+ * launch ends by itself after idle_ms (0 = 20) milliseconds without work and is
+ * started again by the next submit or poll.  Device memory: the server holds
+ * 24 n + n + 16 num_vss bytes per graph for the column state; the caller
+ * provides each request's output and the server admits a request only while the
+ * outputs of submitted, unreleased requests stay within budget_bytes.  Graph
+ * handles must outlive the server; other persistent launches on the device wait
+ * while a server launch runs.
+ * Errors: INVALID_ARGUMENT (count 0 or > 4, null handles, mixed devices, sigma or
+ * slots), NO_DEVICE, TOO_LARGE, OUT_OF_MEMORY, DEVICE. */
+typedef struct blest_server* blest_server_handle;
+blest_status blest_server_create(const blest_handle* graphs, uint32_t count, uint64_t budget_bytes, uint32_t idle_ms,
+                                 blest_server_handle* out);
+
+/* Submits k sources (HOST array, original IDs) on graphs[graph]; levels_out is
+ * DEVICE int32[k * n], row j for sources[j], fully written by the server before
+ * the request reports done.  *ticket identifies the request.  Returns
+ * BLEST_ERR_BUDGET, with nothing submitted, when the request's 4 k n output bytes
+ * would take the unreleased outputs past budget_bytes or when the oldest ring
+ * slot is still held by an unreleased request: release finished requests and
+ * submit again.  Errors: INVALID_ARGUMENT, BUDGET, DEVICE. */
+blest_status blest_server_submit(blest_server_handle s, uint32_t graph, const uint32_t* sources, uint32_t k,
+                                 int32_t* levels_out, uint64_t* ticket);
+
+/* Non-blocking state of a request: *state = 0 waiting, 1 running, 2 done (its
+ * levels are complete in device memory); levels = 1 + its deepest level; the
+ * server iterations that admitted it and after which it finished (either pointer
+ * may be NULL).  Starts a new launch if the request waits and none runs.
+ * Errors: INVALID_ARGUMENT (unknown or released ticket), DEVICE. */
+blest_status blest_server_poll(blest_server_handle s, uint64_t ticket, int32_t* state, uint32_t* levels,
+                               uint32_t* admit_iter, uint32_t* done_iter);
+
+/* Releases a done request: its ring slot and its output bytes return to the
+ * budget (the output buffer stays the caller's).  Errors: INVALID_ARGUMENT (not
+ * done, unknown or already released). */
+blest_status blest_server_release(blest_server_handle s, uint64_t ticket);
+
+typedef struct {
+  uint64_t budget;            /* output bytes the server may have outstanding */
+  uint64_t outstanding;       /* output bytes of submitted, unreleased requests */
+  uint64_t peak_outstanding;  /* largest value `outstanding` reached */
+  uint64_t resident_bytes;    /* device memory held by the server itself */
+  uint64_t submitted;         /* requests submitted so far */
+  uint64_t launches;          /* persistent launches started so far */
+  int32_t running;            /* a launch is in flight */
+  uint32_t grid, block;       /* launch shape */
+} blest_server_stats_t;
+blest_status blest_server_stats(blest_server_handle s, blest_server_stats_t* out);
+
+/* Asks the launch to end once nothing waits or runs and waits for that at most
+ * timeout_ms (0 = 60000) milliseconds; past that it tells the launch to end at
+ * its next level boundary, running requests or not (they never report done), and
+ * waits as long again.  Then frees the server.  If the launch still runs, returns
+ * BLEST_ERR_DEVICE and frees nothing (the call may be repeated).  NULL is
+ * ignored. */
+blest_status blest_server_destroy(blest_server_handle s, uint32_t timeout_ms);
+
 /* Changes the launch settings of a built handle without rebuilding it: update
  * scheme (BLEST_UPDATE_*), threads per workgroup, workgroups per compute unit and
  * VSS group depth, with the meanings (and 0 = default) of blest_options.  Used by
@@ -221,7 +295,8 @@ blest_status blest_level_stats(int32_t device, const int32_t* levels, uint32_t k
  * row, its unpadded slices (4-byte row ID + sigma/8-byte mask), its frontier (the
  * sigma-bit chunk, or sigma 64-bit words when k > 1) and 8 bytes per VSS (queue
  * entry + VSS metadata); plus, for k = 1, the lazy scheme's per-level sweep of the
- * two n-bit visited bitmaps and the 4n-byte level initialisation; for k > 1, per
+ * two n-bit visited bitmaps, the 4n-byte level initialisation and 4 bytes per
+ * reached vertex (its level write); for k > 1, per
  * iteration, a 25n-byte vertex sweep when the queue holds at least 1/16 of the
  * VSSs, else n state bytes plus 26 bytes per vertex changed in the iteration and 8
  * per vertex leaving the frontier; the 4kn-byte initialisation and 4 bytes per

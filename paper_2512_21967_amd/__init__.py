@@ -26,9 +26,18 @@ LDS_OFF = 0xFFFFFFFF
 EXPORT = {"new_id": (0, np.uint32), "real_ptrs": (1, np.uint32), "virtual_to_real": (2, np.uint32),
           "vss_begin": (3, np.uint32), "row_ids": (4, np.uint32), "masks": (5, np.uint8),
           "vss_range": (6, np.uint8), "order_id": (7, np.uint32)}
-EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_bfs_multi", "blest_bfs_many",
-                    "blest_batch_create", "blest_batch_run", "blest_batch_destroy", "blest_configure", "blest_stats", "blest_footprint", "blest_export", "blest_model_bytes", "blest_level_stats", "blest_destroy",
-                    "blest_status_string")
+EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_bfs_multi",
+                    "blest_bfs_many",
+                    "blest_batch_create", "blest_batch_run", "blest_batch_destroy", "blest_server_create",
+                    "blest_server_submit", "blest_server_poll", "blest_server_release", "blest_server_stats",
+                    "blest_server_destroy", "blest_configure", "blest_stats", "blest_footprint", "blest_export",
+                    "blest_model_bytes", "blest_level_stats", "blest_destroy", "blest_status_string")
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_uint64), ("outstanding", ctypes.c_uint64), ("peak_outstanding", ctypes.c_uint64),
+                ("resident_bytes", ctypes.c_uint64), ("submitted", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("running", ctypes.c_int32), ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32)]
 
 
 class BlestError(RuntimeError):
@@ -55,7 +64,9 @@ class Stats(ctypes.Structure):
                 ("bvss_device_bytes", ctypes.c_uint64), ("bvss_bytes_table3", ctypes.c_uint64),
                 ("reorder_seconds", ctypes.c_double), ("build_seconds", ctypes.c_double),
                 ("hubs_sorted", ctypes.c_int32), ("lds_bytes", ctypes.c_uint32),
-                ("lds_chunk_words", ctypes.c_uint32), ("hub_cpos", ctypes.c_uint32)]
+                ("lds_chunk_words", ctypes.c_uint32), ("hub_cpos", ctypes.c_uint32),
+                ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32), ("kernel_vgprs", ctypes.c_uint32),
+                ("blocks_per_cu_runtime", ctypes.c_uint32), ("blocks_per_cu_own", ctypes.c_uint32)]
 
 
 _lib = None
@@ -88,6 +99,18 @@ def lib():
     L.blest_batch_run.restype = ctypes.c_int
     L.blest_batch_destroy.argtypes = [vp]
     L.blest_batch_destroy.restype = None
+    L.blest_server_create.argtypes = [ctypes.POINTER(vp), u32, u64, u32, ctypes.POINTER(vp)]
+    L.blest_server_create.restype = ctypes.c_int
+    L.blest_server_submit.argtypes = [vp, u32, p32, u32, vp, ctypes.POINTER(u64)]
+    L.blest_server_submit.restype = ctypes.c_int
+    L.blest_server_poll.argtypes = [vp, u64, ctypes.POINTER(i32), p32, p32, p32]
+    L.blest_server_poll.restype = ctypes.c_int
+    L.blest_server_release.argtypes = [vp, u64]
+    L.blest_server_release.restype = ctypes.c_int
+    L.blest_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.blest_server_stats.restype = ctypes.c_int
+    L.blest_server_destroy.argtypes = [vp, u32]
+    L.blest_server_destroy.restype = ctypes.c_int
     L.blest_configure.argtypes = [vp, i32, u32, u32, u32]
     L.blest_configure.restype = ctypes.c_int
     L.blest_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -369,6 +392,66 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None:
             lib().blest_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+BLEST_ERR_BUDGET = 5
+
+
+class DeviceServer:
+    """The continuous-batching server of libblest (blest_server_*): one persistent
+    launch on its own stream serving requests of 1..64 sources on up to 4 resident
+    graphs, admitted into free source columns at level boundaries.  Argument
+    marshalling only; the loop that feeds it is ``paper_2512_21967_amd.serve``."""
+
+    WAITING, RUNNING, DONE = 0, 1, 2
+
+    def __init__(self, graphs, budget_bytes: int, idle_ms: int = 20):
+        self.graphs = list(graphs)
+        hs = (ctypes.c_void_p * len(self.graphs))(*[g.handle.value for g in self.graphs])
+        h = ctypes.c_void_p()
+        _check("blest_server_create", lib().blest_server_create(hs, len(self.graphs), int(budget_bytes), int(idle_ms),
+                                                                ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, graph: int, sources, levels):
+        """Ticket of the submitted request, or None when the budget or the request
+        ring is full (nothing was submitted)."""
+        src = np.ascontiguousarray(sources, dtype=np.uint32)
+        _require_int32_cuda(levels, src.size * self.graphs[graph].n, "levels")
+        t = ctypes.c_uint64()
+        rc = lib().blest_server_submit(self._h, int(graph), _p32(src), int(src.size),
+                                       ctypes.c_void_p(levels.data_ptr()), ctypes.byref(t))
+        if rc == BLEST_ERR_BUDGET:
+            return None
+        _check("blest_server_submit", rc)
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(state, levels, admit_iter, done_iter); state WAITING, RUNNING or DONE."""
+        st = ctypes.c_int32()
+        lv, a, d = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check("blest_server_poll", lib().blest_server_poll(self._h, int(ticket), ctypes.byref(st), ctypes.byref(lv),
+                                                            ctypes.byref(a), ctypes.byref(d)))
+        return int(st.value), int(lv.value), int(a.value), int(d.value)
+
+    def release(self, ticket: int):
+        _check("blest_server_release", lib().blest_server_release(self._h, int(ticket)))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check("blest_server_stats", lib().blest_server_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in ServerStats._fields_}
+
+    def close(self, timeout_ms: int = 60000):
+        if getattr(self, "_h", None) is not None:
+            _check("blest_server_destroy", lib().blest_server_destroy(self._h, int(timeout_ms)))
             self._h = None
 
     def __del__(self):

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -69,6 +70,7 @@ constexpr uint32_t kLdsMinQueue = 4096;
 }  // namespace
 
 struct blest_batch;
+struct blest_server;
 
 struct blest_graph {
   blest_options opt{};
@@ -92,6 +94,8 @@ struct blest_graph {
   uint32_t nranges = 1, range_len = 0, range_words = 0;
   uint32_t lds_cap_words = 0, lds_cshift = 0, hub_cpos = 0;
   uint32_t grid = 0, block = 0;
+  uint32_t occ_api = 0, occ_own = 0;  // workgroups per CU: runtime answer, own resource bound
+  int num_regs = 0;                   // vector registers of the single-source kernel
   std::mutex ws_mu;
   std::map<void*, std::unique_ptr<SingleWorkspace>> single_ws;
   std::map<void*, std::unique_ptr<MultiWorkspace>> multi_ws;
@@ -106,6 +110,33 @@ struct blest_batch {
   int device = -1;
   uint32_t g = 0, max_n = 0, sigma = 8, slots = 4;
   DevBuf d_items, d_queues;
+};
+
+// A continuous-batching server over resident graphs (kernels_serve.hip).
+struct blest_server {
+  int device = -1;
+  uint32_t sigma = 8, slots = 2, grid = 0, block = 1024;
+  std::vector<blest_graph*> graphs;
+  struct GraphState {
+    DevBuf vis, front, touched, queue;
+  };
+  std::vector<std::unique_ptr<GraphState>> gs;
+  DevBuf state, ctrl;
+  ServeMailbox* mb = nullptr;      // pinned host memory, coherent
+  ServeMailbox* mb_dev = nullptr;  // its device address
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;         // recorded after every launch
+  bool launched = false;
+  uint64_t budget = 0, outstanding = 0, peak = 0, resident = 0;
+  uint32_t next_ticket = 0, idle_limit = 0;
+  uint64_t launches = 0;
+  uint64_t charge[kServeRing] = {};
+  std::mutex mu;
+  ~blest_server() {
+    if (ev) (void)hipEventDestroy(ev);
+    if (stream) (void)hipStreamDestroy(stream);
+    if (mb) (void)hipHostFree(mb);
+  }
 };
 
 namespace {
@@ -140,9 +171,9 @@ bool valid_options(const blest_options& o) {
   if (o.update < BLEST_UPDATE_AUTO || o.update > BLEST_UPDATE_LAZY) return false;
   if (o.block % 64 != 0 || o.block > 1024) return false;
   if (o.blocks_per_cu > 16) return false;
-  // Persistent grids fill at most half of a compute unit's wave slots: a launch
-  // that filled all of them (1024 x 2) hung once, cause not identified.
-  if ((uint64_t)o.block * (o.blocks_per_cu ? o.blocks_per_cu : 1) > 1024) return false;
+  // at most a compute unit's 2048 threads; the grid is further clamped to what the
+  // kernel's registers and LDS let the CU hold at once (own_blocks_per_cu)
+  if ((uint64_t)o.block * (o.blocks_per_cu ? o.blocks_per_cu : 1) > 2048) return false;
   if (o.group != 1 && o.group != 2 && o.group != 4) return false;
   if (o.ranges > kMaxRanges || (o.ranges & (o.ranges - 1)) != 0) return false;
   if (o.hubs > 2) return false;
@@ -159,6 +190,7 @@ hipError_t upload(DevBuf& d, const std::vector<T>& h) {
 }
 
 blest_status set_grid(blest_graph* g);
+hipError_t serial_event(int device);
 
 blest_status to_device(blest_graph* g) {
   if (hipSetDevice(g->device) != hipSuccess) return BLEST_ERR_NO_DEVICE;
@@ -180,8 +212,39 @@ blest_status to_device(blest_graph* g) {
   if (e != hipSuccess) return BLEST_ERR_DEVICE;
   blest_status st = set_grid(g);
   if (st != BLEST_OK) return st;
+  if (serial_event(g->device) != hipSuccess) return BLEST_ERR_DEVICE;
   g->on_device = true;
   return BLEST_OK;
+}
+
+// Workgroups of `block` threads that one compute unit can hold at once by the
+// kernel's own register, scratch and LDS use, under gfx950's rules: each SIMD
+// has 512 vector registers per lane (architectural and accumulation registers
+// together), allocated in granules of 8, and 800 scalar registers allocated in
+// granules of 16, and runs at most 8 wavefronts; a workgroup's wavefronts are
+// spread evenly over the CU's 4 SIMDs; a CU has 160 KiB of LDS.  The runtime
+// reports no scalar-register count, and every persistent kernel of this library
+// allocates 98-106 of them, which caps it at 7 wavefronts per SIMD: two
+// 1024-thread workgroups (8 per SIMD) never fit one CU, whatever the vector
+// registers allow.  The runtime's occupancy answer is not taken alone: a
+// persistent grid larger than what is really resident never gets past its
+// first grid barrier.  Kernels with a private segment (scratch) are held to one
+// workgroup per CU, since scratch wavefronts are limited per queue as well.
+uint32_t own_blocks_per_cu(const void* kernel, uint32_t block, uint32_t dyn_lds, int* num_regs) {
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, kernel) != hipSuccess) return 0;
+  *num_regs = fa.numRegs;
+  constexpr uint32_t kRegsPerLane = 512, kGranule = 8, kMaxWavesPerSimd = 7, kSimds = 4;
+  constexpr uint64_t kLdsPerCu = 160ull * 1024;
+  const uint32_t regs = std::max<uint32_t>(kGranule, ((uint32_t)std::max(fa.numRegs, 1) + kGranule - 1) / kGranule * kGranule);
+  const uint32_t waves_per_simd = std::min(kMaxWavesPerSimd, kRegsPerLane / regs);
+  const uint32_t waves = (block + 63) / 64;
+  const uint32_t per_simd = (waves + kSimds - 1) / kSimds;  // a workgroup's wavefronts on each SIMD
+  uint32_t nb = per_simd ? waves_per_simd / per_simd : 0;
+  const uint64_t lds = (uint64_t)fa.sharedSizeBytes + dyn_lds;
+  if (lds) nb = std::min<uint64_t>(nb, kLdsPerCu / lds);
+  if (fa.localSizeBytes > 0) nb = std::min<uint32_t>(nb, 1);
+  return nb;
 }
 
 // Persistent grid: co-resident workgroups, capped at blocks_per_cu per CU.
@@ -208,20 +271,22 @@ blest_status set_grid(blest_graph* g) {
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * g->range_words)) != hipSuccess)
       return BLEST_ERR_DEVICE;
   }
+  const uint32_t dyn = lds ? 4 * g->range_words : 0;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)g->block, lds ? 4 * g->range_words : 0) !=
-          hipSuccess ||
-      nb <= 0)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)g->block, dyn) != hipSuccess || nb <= 0)
     return BLEST_ERR_DEVICE;
-  const uint32_t per_cu = std::min<uint32_t>((uint32_t)nb, g->opt.blocks_per_cu);
+  g->occ_api = (uint32_t)nb;
+  g->occ_own = own_blocks_per_cu(k, g->block, dyn, &g->num_regs);
+  const uint32_t per_cu = std::min({(uint32_t)nb, g->occ_own, g->opt.blocks_per_cu});
   g->grid = per_cu * (uint32_t)cus / g->nranges * g->nranges;
   if (g->grid == 0) return BLEST_ERR_DEVICE;
-  int nbm = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbm, bfs_multi_kernel_symbol(b.sigma, b.slots), (int)g->block, 0) !=
-          hipSuccess ||
-      nbm <= 0)
+  const void* km = bfs_multi_kernel_symbol(b.sigma, b.slots);
+  int nbm = 0, regs_m = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbm, km, (int)g->block, 0) != hipSuccess || nbm <= 0)
     return BLEST_ERR_DEVICE;
-  g->multi_grid = std::min<uint32_t>((uint32_t)nbm, g->opt.blocks_per_cu) * (uint32_t)cus;
+  const uint32_t own_m = own_blocks_per_cu(km, g->block, 0, &regs_m);
+  g->multi_grid = std::min({(uint32_t)nbm, own_m, g->opt.blocks_per_cu}) * (uint32_t)cus;
+  if (g->multi_grid == 0) return BLEST_ERR_DEVICE;
   return BLEST_OK;
 }
 
@@ -270,20 +335,23 @@ MultiWorkspace* multi_workspace(blest_graph* g, void* stream, blest_status* st) 
   return raw;
 }
 
+// Creates the device's tail event (at upload time, so that launches create nothing).
+hipError_t serial_event(int device) {
+  DeviceSerial& ds = g_serial[device & 63];
+  std::lock_guard<std::mutex> lk(ds.mu);
+  if (ds.last) return hipSuccess;
+  return hipEventCreateWithFlags(&ds.last, hipEventDisableTiming);
+}
+
 // Makes `stream` wait for the previous persistent launch on this device, runs
 // `launch`, and records the new tail event.
 template <class F>
 hipError_t serial_launch(int device, hipStream_t stream, F&& launch) {
   DeviceSerial& ds = g_serial[device & 63];
   std::lock_guard<std::mutex> lk(ds.mu);
-  hipError_t e = hipSuccess;
-  if (!ds.last) {
-    e = hipEventCreateWithFlags(&ds.last, hipEventDisableTiming);
-    if (e != hipSuccess) return e;
-  } else {
-    e = hipStreamWaitEvent(stream, ds.last, 0);
-    if (e != hipSuccess) return e;
-  }
+  if (!ds.last) return hipErrorNotReady;  // created when a handle is uploaded (serial_event)
+  hipError_t e = hipStreamWaitEvent(stream, ds.last, 0);
+  if (e != hipSuccess) return e;
   e = launch();
   if (e != hipSuccess) return e;
   return hipEventRecord(ds.last, stream);
@@ -309,6 +377,45 @@ BfsParams base_params(const blest_graph* g) {
   p.lds_cshift = g->lds_cshift;
   p.lds_min_len = std::min<uint32_t>(kLdsMinQueue, std::max<uint32_t>(1, p.range_words / 16));
   return p;
+}
+
+// Starts a server launch unless one is running.  Caller holds sv->mu.
+hipError_t server_ensure_running(blest_server* sv) {
+  if (sv->launched && hipEventQuery(sv->ev) == hipErrorNotReady) return hipSuccess;
+  ServeParams p{};
+  p.ngraphs = (uint32_t)sv->graphs.size();
+  for (uint32_t i = 0; i < p.ngraphs; ++i) {
+    const blest_graph* h = sv->graphs[i];
+    ServeGraph& G = p.g[i];
+    G.row_ids = h->d_row_ids.as<uint32_t>();
+    G.masks = h->d_masks.p;
+    G.vss_beg = h->d_vss_beg.as<uint32_t>();
+    G.v2r = h->d_v2r.as<uint32_t>();
+    G.real_ptrs = h->d_real_ptrs.as<uint32_t>();
+    G.orig_id = h->identity ? nullptr : h->d_orig_id.as<uint32_t>();
+    G.vis = sv->gs[i]->vis.as<unsigned long long>();
+    G.front = sv->gs[i]->front.as<unsigned long long>();
+    G.touched = sv->gs[i]->touched.as<uint8_t>();
+    G.queue = sv->gs[i]->queue.as<uint32_t>();
+    G.n = h->n;
+    G.num_sets = h->bvss.num_sets;
+    G.num_vss = h->bvss.num_vss;
+    G.qcap = 2 * std::max<uint32_t>(h->bvss.num_vss, 1);
+  }
+  p.idle_limit = sv->idle_limit;
+  p.mb = sv->mb_dev;
+  p.st = sv->state.as<ServeState>();
+  p.ctrl = sv->ctrl.as<uint32_t>();
+  if (hipSetDevice(sv->device) != hipSuccess) return hipErrorInvalidDevice;
+  hipError_t e = serial_launch(sv->device, sv->stream, [&] {
+    return launch_serve(p, sv->sigma, sv->slots, sv->grid, sv->block, sv->stream);
+  });
+  if (e == hipSuccess) e = hipEventRecord(sv->ev, sv->stream);
+  if (e == hipSuccess) {
+    sv->launched = true;
+    ++sv->launches;
+  }
+  return e;
 }
 
 }  // namespace
@@ -685,6 +792,11 @@ blest_status blest_stats(blest_handle h, blest_stats_t* o) {
   o->reorder_seconds = h->reorder_seconds;
   o->build_seconds = h->build_seconds;
   o->hubs_sorted = h->hubs_sorted;
+  o->grid = h->grid;
+  o->block = h->block;
+  o->kernel_vgprs = (uint32_t)std::max(h->num_regs, 0);
+  o->blocks_per_cu_runtime = h->occ_api;
+  o->blocks_per_cu_own = h->occ_own;
   o->lds_bytes = h->lazy ? 4 * h->range_words : 0;
   o->lds_chunk_words = h->lazy && h->range_words ? 1u << h->lds_cshift : 0;
   o->hub_cpos = h->hub_cpos;
@@ -801,7 +913,7 @@ blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k
   const uint64_t iters = (uint64_t)maxl + 1;
   if (k == 1) {
     if (h->lazy) total += iters * 2ull * ((n + 7) / 8);  // Stage 2 reads both visited bitmaps
-    total += 4ull * n;                                      // level initialisation
+    total += 4ull * n + 4ull * reached;                     // level initialisation + level writes
   } else {
     // Stage 2 per iteration i: a dense iteration (queue >= 1/16 of the VSSs) sweeps
     // every vertex (visited pair, frontier word, state byte: 25 B); a sparse one
@@ -842,6 +954,184 @@ blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k
     total += 4ull * k * n + n + 4ull * reached;            // level, visited and state initialisation + level writes
   }
   *bytes = total;
+  return BLEST_OK;
+}
+
+blest_status blest_server_create(const blest_handle* hs, uint32_t count, uint64_t budget_bytes, uint32_t idle_ms,
+                                 blest_server_handle* out) {
+  if (!out) return BLEST_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (!hs || count == 0 || count > kServeMaxGraphs) return BLEST_ERR_INVALID_ARGUMENT;
+  for (uint32_t i = 0; i < count; ++i) {
+    if (!hs[i]) return BLEST_ERR_INVALID_ARGUMENT;
+    if (!hs[i]->on_device) return BLEST_ERR_NO_DEVICE;
+    if (hs[i]->device != hs[0]->device || hs[i]->bvss.sigma != hs[0]->bvss.sigma ||
+        hs[i]->bvss.slots != hs[0]->bvss.slots)
+      return BLEST_ERR_INVALID_ARGUMENT;
+    if (hs[i]->bvss.num_vss > 0x7FFFFFFFu / 2 || hs[i]->bvss.num_sets >= (1u << 28)) return BLEST_ERR_TOO_LARGE;
+  }
+  try {
+    std::unique_ptr<blest_server> sv(new blest_server);
+    sv->device = hs[0]->device;
+    if (hipSetDevice(sv->device) != hipSuccess) return BLEST_ERR_DEVICE;
+    sv->sigma = hs[0]->bvss.sigma;
+    sv->slots = hs[0]->bvss.slots;
+    sv->budget = budget_bytes;
+    sv->idle_limit = (idle_ms ? idle_ms : 20) * 100000u;  // s_memrealtime runs at 100 MHz
+    hipError_t e = hipSuccess;
+    for (uint32_t i = 0; i < count && e == hipSuccess; ++i) {
+      blest_graph* h = hs[i];
+      sv->graphs.push_back(h);
+      auto st = std::make_unique<blest_server::GraphState>();
+      const uint64_t qcap = 2ull * std::max<uint32_t>(h->bvss.num_vss, 1);
+      e = st->vis.alloc(16ull * h->n);
+      if (e == hipSuccess) e = st->front.alloc(8ull * h->n);
+      if (e == hipSuccess) e = st->touched.alloc((uint64_t)std::max<uint32_t>(h->bvss.num_sets, 1) * h->bvss.sigma);
+      if (e == hipSuccess) e = st->queue.alloc(2 * 4 * qcap);
+      if (e == hipSuccess) e = hipMemset(st->vis.p, 0, st->vis.bytes);
+      if (e == hipSuccess) e = hipMemset(st->front.p, 0, st->front.bytes);
+      if (e == hipSuccess) e = hipMemset(st->touched.p, 0, st->touched.bytes);
+      sv->resident += st->vis.bytes + st->front.bytes + st->touched.bytes + st->queue.bytes;
+      sv->gs.push_back(std::move(st));
+    }
+    if (e == hipSuccess) e = sv->state.alloc(sizeof(ServeState));
+    if (e == hipSuccess) e = hipMemset(sv->state.p, 0, sizeof(ServeState));
+    if (e == hipSuccess) {
+      const uint32_t one = 1;  // iterations are numbered from 1
+      e = hipMemcpy(reinterpret_cast<char*>(sv->state.p) + offsetof(ServeState, iter), &one, 4,
+                    hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = sv->ctrl.alloc(4ull * kServeCtrlWords);
+    if (e == hipSuccess) e = hipMemset(sv->ctrl.p, 0, 4ull * kServeCtrlWords);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sv->mb), sizeof(ServeMailbox),
+                                           hipHostMallocCoherent | hipHostMallocMapped);
+    if (e == hipSuccess) {
+      std::memset(sv->mb, 0, sizeof(ServeMailbox));
+      e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sv->mb_dev), sv->mb, 0);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? BLEST_ERR_OUT_OF_MEMORY : BLEST_ERR_DEVICE;
+    sv->resident += sizeof(ServeState) + 4ull * kServeCtrlWords;
+    const void* k = serve_kernel_symbol(sv->sigma, sv->slots);
+    int cus = 0, nb = 0, regs = 0;
+    if (!k || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, sv->device) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)sv->block, 0) != hipSuccess || nb <= 0)
+      return BLEST_ERR_DEVICE;
+    const uint32_t own = own_blocks_per_cu(k, sv->block, 0, &regs);
+    sv->grid = std::min<uint32_t>({(uint32_t)nb, own, 1u}) * (uint32_t)cus;
+    if (sv->grid == 0) return BLEST_ERR_DEVICE;
+    *out = sv.release();
+    return BLEST_OK;
+  } catch (const std::bad_alloc&) {
+    return BLEST_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    return BLEST_ERR_INTERNAL;
+  }
+}
+
+blest_status blest_server_submit(blest_server_handle sv, uint32_t graph, const uint32_t* sources, uint32_t k,
+                                 int32_t* levels_out, uint64_t* ticket) {
+  if (!sv || !sources || !levels_out || !ticket || graph >= sv->graphs.size() || k == 0 || k > kServeCols)
+    return BLEST_ERR_INVALID_ARGUMENT;
+  const blest_graph* h = sv->graphs[graph];
+  for (uint32_t j = 0; j < k; ++j)
+    if (sources[j] >= h->n) return BLEST_ERR_INVALID_ARGUMENT;
+  try {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const uint64_t bytes = 4ull * k * h->n;
+    const uint32_t r = sv->next_ticket % kServeRing;
+    ServeSlot* slot = &sv->mb->slot[r];
+    if (sv->outstanding + bytes > sv->budget ||
+        __atomic_load_n(&slot->state, __ATOMIC_ACQUIRE) != 0)  // ring slot still held by an unreleased request
+      return BLEST_ERR_BUDGET;
+    slot->graph = graph;
+    slot->k = k;
+    slot->admit_iter = slot->done_iter = slot->levels = 0;
+    slot->out = reinterpret_cast<uint64_t>(levels_out);
+    for (uint32_t j = 0; j < k; ++j) slot->src[j] = h->new_id[sources[j]];
+    __atomic_store_n(&slot->state, 1u, __ATOMIC_RELAXED);
+    __atomic_store_n(&sv->mb->submitted, sv->next_ticket + 1, __ATOMIC_RELEASE);
+    *ticket = sv->next_ticket++;
+    sv->charge[r] = bytes;
+    sv->outstanding += bytes;
+    sv->peak = std::max(sv->peak, sv->outstanding);
+    return server_ensure_running(sv) == hipSuccess ? BLEST_OK : BLEST_ERR_DEVICE;
+  } catch (...) {
+    return BLEST_ERR_INTERNAL;
+  }
+}
+
+blest_status blest_server_poll(blest_server_handle sv, uint64_t ticket, int32_t* state, uint32_t* levels,
+                               uint32_t* admit_iter, uint32_t* done_iter) {
+  if (!sv || !state) return BLEST_ERR_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (ticket >= sv->next_ticket || sv->next_ticket - ticket > kServeRing) return BLEST_ERR_INVALID_ARGUMENT;
+  const ServeSlot* slot = &sv->mb->slot[ticket % kServeRing];
+  const uint32_t s = __atomic_load_n(&slot->state, __ATOMIC_ACQUIRE);
+  if (s == 0) return BLEST_ERR_INVALID_ARGUMENT;  // released
+  *state = (int32_t)s - 1;                        // 0 waiting, 1 running, 2 done
+  if (levels) *levels = slot->levels;
+  if (admit_iter) *admit_iter = slot->admit_iter;
+  if (done_iter) *done_iter = slot->done_iter;
+  // a launch that ended (idle limit) just before this request was published is
+  // followed by a new one
+  if (s == 1 && server_ensure_running(sv) != hipSuccess) return BLEST_ERR_DEVICE;
+  return BLEST_OK;
+}
+
+blest_status blest_server_release(blest_server_handle sv, uint64_t ticket) {
+  if (!sv) return BLEST_ERR_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (ticket >= sv->next_ticket || sv->next_ticket - ticket > kServeRing) return BLEST_ERR_INVALID_ARGUMENT;
+  const uint32_t r = ticket % kServeRing;
+  ServeSlot* slot = &sv->mb->slot[r];
+  if (__atomic_load_n(&slot->state, __ATOMIC_ACQUIRE) != 3) return BLEST_ERR_INVALID_ARGUMENT;
+  __atomic_store_n(&slot->state, 0u, __ATOMIC_RELEASE);
+  sv->outstanding -= sv->charge[r];
+  sv->charge[r] = 0;
+  return BLEST_OK;
+}
+
+blest_status blest_server_stats(blest_server_handle sv, blest_server_stats_t* out) {
+  if (!sv || !out) return BLEST_ERR_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->budget = sv->budget;
+  out->outstanding = sv->outstanding;
+  out->peak_outstanding = sv->peak;
+  out->resident_bytes = sv->resident;
+  out->submitted = sv->next_ticket;
+  out->launches = sv->launches;
+  out->running = sv->launched && hipEventQuery(sv->ev) == hipErrorNotReady;
+  out->grid = sv->grid;
+  out->block = sv->block;
+  return BLEST_OK;
+}
+
+blest_status blest_server_destroy(blest_server_handle sv, uint32_t timeout_ms) {
+  if (!sv) return BLEST_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    __atomic_store_n(&sv->mb->stop, 1u, __ATOMIC_RELEASE);
+  }
+  // the launch ends once nothing waits or runs; past the time limit it is told to
+  // end at its next level boundary (stop = 2), running requests or not
+  const double limit = (timeout_ms ? timeout_ms : 60000) / 1000.0;
+  double t0 = now_s();
+  bool aborted = false;
+  while (sv->launched && hipEventQuery(sv->ev) == hipErrorNotReady) {
+    if (now_s() - t0 > limit) {
+      if (aborted) return BLEST_ERR_DEVICE;  // still running: nothing freed
+      __atomic_store_n(&sv->mb->stop, 2u, __ATOMIC_RELEASE);
+      aborted = true;
+      t0 = now_s();
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(200));
+  }
+  (void)hipSetDevice(sv->device);
+  delete sv;
   return BLEST_OK;
 }
 

@@ -84,6 +84,90 @@ hipError_t launch_bfs_multi(const MultiParams& p, uint32_t sigma, uint32_t slots
                             hipStream_t stream);
 const void* bfs_multi_kernel_symbol(uint32_t sigma, uint32_t slots);
 
+// ---- continuous-batching server (kernels_serve.hip) ----
+// One persistent launch serves BFS requests of 1..64 sources on up to
+// kServeMaxGraphs resident graphs.  Every graph has 64 source columns (one bit of
+// a 64-bit word per vertex, as in the k-source kernel); a request takes k free
+// columns of its graph at a level boundary and frees them when its last column
+// stops growing, so requests that arrive while others run join the running
+// sweeps instead of waiting for them.
+constexpr uint32_t kServeMaxGraphs = 4;
+constexpr uint32_t kServeCols = 64;
+constexpr uint32_t kServeRing = 256;  // request slots of the mailbox ring
+
+// Request slot (host memory, coherent).  The host fills a free slot and then
+// publishes it by advancing ServeMailbox::submitted; afterwards only the device
+// writes the slot (state, admit_iter, done_iter, levels) until the host sees
+// state 3 and frees it.
+struct ServeSlot {
+  uint32_t state;       // 0 free, 1 submitted, 2 admitted, 3 done
+  uint32_t graph;       // index of the resident graph
+  uint32_t k;           // sources (1..64)
+  uint32_t admit_iter;  // server iteration whose level boundary admitted the request
+  uint32_t done_iter;   // iteration after which its last column stopped growing
+  uint32_t levels;      // 1 + largest level over its rows
+  uint64_t out;         // device int32[k * n], row j for src[j], original IDs
+  uint32_t src[kServeCols];  // sources, new labels
+};
+
+struct ServeMailbox {
+  uint32_t submitted;  // tickets [0, submitted) are published (host writes)
+  uint32_t stop;       // host: 1 = end the launch once no request is waiting or running
+  uint32_t pad[30];
+  ServeSlot slot[kServeRing];
+};
+
+struct ServeGraph {
+  const uint32_t* row_ids;
+  const void* masks;
+  const uint32_t* vss_beg;
+  const uint32_t* v2r;
+  const uint32_t* real_ptrs;
+  const uint32_t* orig_id;    // nullptr = identity
+  unsigned long long* vis;    // 2 * n: (current, next) per vertex
+  unsigned long long* front;  // n
+  uint8_t* touched;           // num_sets * sigma state bytes
+  uint32_t* queue;            // 2 * qcap
+  uint32_t n, num_sets, num_vss, qcap;
+};
+
+// Device-resident server state; persists across launches (zeroed at creation).
+struct ServeState {
+  uint32_t consumed;   // tickets below this are admitted or done
+  uint32_t seen;       // tickets below this are copied into `slot`
+  uint32_t iter;       // server iterations so far (monotone across launches)
+  uint32_t exit;       // set by the control step: the launch ends
+  uint32_t n_admit;    // columns admitted at this level boundary
+  uint32_t launches;   // launches that started
+  uint32_t pad0[2];
+  unsigned long long active[kServeMaxGraphs];  // columns in use
+  unsigned long long alive[kServeMaxGraphs];   // columns that grew in the last iteration
+  unsigned long long dirty[kServeMaxGraphs];   // freed columns whose bits are still set
+  unsigned long long admitted[kServeMaxGraphs];  // columns admitted at this boundary
+  uint64_t col_out[kServeMaxGraphs][kServeCols];   // row pointer of each column
+  uint32_t col_ticket[kServeMaxGraphs][kServeCols];
+  uint32_t col_start[kServeMaxGraphs][kServeCols];  // iteration of admission
+  uint32_t remaining[kServeRing];                   // running columns per slot
+  uint32_t maxlev[kServeRing];
+  ServeSlot slot[kServeRing];                       // device copies of published slots
+  uint32_t adm_gc[kServeMaxGraphs * kServeCols];    // (graph << 8) | column
+  uint32_t adm_src[kServeMaxGraphs * kServeCols];   // source (new label)
+};
+
+struct ServeParams {
+  ServeGraph g[kServeMaxGraphs];
+  uint32_t ngraphs;
+  uint32_t idle_limit;   // realtime ticks (100 MHz) without work before the launch ends
+  ServeMailbox* mb;      // host memory, coherent
+  ServeState* st;        // device memory
+  uint32_t* ctrl;        // barrier counters and queue lengths (kServeCtrlWords)
+};
+constexpr uint32_t kServeCtrlWords = kQlen + 3 * kServeMaxGraphs * kLine;
+
+hipError_t launch_serve(const ServeParams& p, uint32_t sigma, uint32_t slots, uint32_t grid, uint32_t block,
+                        hipStream_t stream);
+const void* serve_kernel_symbol(uint32_t sigma, uint32_t slots);
+
 // Many independent single-source BFSs in one ordinary launch: workgroup i runs
 // item i start to finish, with its bitmaps in LDS and only workgroup barriers.
 struct ManyItem {

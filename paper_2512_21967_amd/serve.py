@@ -1,23 +1,24 @@
-"""Serving loop: BFS queries against device-resident graphs, admitted by HBM
-footprint and batched dynamically.
+"""Serving loop: BFS queries against device-resident graphs with continuous
+batching on the device.
 
-A request names a resident graph and 1..64 sources.  Requests for the same graph
-that are waiting when a launch slot frees up are packed, oldest first, into the
-columns of one k-source BFS (k <= 64, ``blest_bfs_multi``; a lone single source
-uses ``blest_bfs``), as long as the batch's device footprint
-(``blest_footprint``: bitmaps, queues and k*n*4 bytes of levels) fits the free part
-of the HBM budget.  Requests that arrive while batches run join the next batch
-that has room: a slot and budget are released as soon as a batch's completion
-event fires.  Batches are issued on a small pool of streams, so the host forms
-and launches the next batch, and the device copies or reduces finished results,
-while the current BFS runs.  Persistent BFS launches themselves run one at a time
-on the device (libblest serialises them so that each one's workgroups are all
-resident).
+A request names a resident graph and 1..64 sources.  The device side is libblest's
+server (``blest_server_*``): one persistent launch that keeps 64 source columns
+per resident graph and, at every level boundary, admits waiting requests into
+free columns, so a request that arrives while others run joins the running
+sweep; its columns advance one level per server iteration alongside the others'
+and are freed when they stop growing.  Each request's rows are the k-source BFS
+of its sources (Section 2's stacked frontiers), identical to the request run
+alone.
 
-Latency is measured from a request's arrival to the moment its levels are ready
-on the device (the completion event of its batch, mapped to the host clock).
-Each request's levels are row views into its batch's output and are identical to
-what the request would get alone: every column of a k-source BFS is independent.
+This host loop only moves requests from the trace into the server: oldest first,
+each as soon as its output (k * n * 4 bytes, allocated from PyTorch's pool when the
+request is submitted) fits the HBM budget together with the outputs of submitted
+requests that have not been released.  A finished request's output stays charged
+until the caller releases it (``keep=True``) or until ``on_done`` has consumed it
+(``keep=False``: released right after ``on_done`` returns).
+
+Latency is measured from a request's arrival to the moment the host sees it done
+(its levels are then complete in device memory).
 """
 from __future__ import annotations
 
@@ -34,9 +35,14 @@ class Request:
     graph: str
     sources: np.ndarray            # uint32[k]
     arrival: float                 # host seconds (perf_counter base)
-    levels: object = None          # int32 CUDA tensor [k, n] once done
+    levels: object = None          # int32 CUDA tensor [k, n] once submitted
+    submitted_at: float | None = None
     done_at: float | None = None
-    batch_id: int | None = None
+    ticket: int | None = None
+    depth: int = 0                 # 1 + deepest level over the request's rows
+    admit_iter: int = 0            # server iteration that admitted it
+    done_iter: int = 0             # server iteration after which it finished
+    released: bool = False
 
     @property
     def k(self) -> int:
@@ -45,34 +51,6 @@ class Request:
     @property
     def latency(self) -> float | None:
         return None if self.done_at is None else self.done_at - self.arrival
-
-
-def plan_batch(pending, free_bytes: int, footprint, max_k: int = 64):
-    """Chooses the next batch.
-
-    pending: dict graph -> deque of waiting Requests (oldest first).
-    footprint(graph, k) -> device bytes a k-source call on that graph needs.
-    Picks the graph whose oldest waiting request arrived first, then packs that
-    graph's requests in arrival order while the column count stays <= max_k and
-    the footprint fits free_bytes.  Returns (graph, [requests]) or None when the
-    oldest request does not fit yet (head-of-line order is kept, so no request
-    starves)."""
-    heads = [(q[0].arrival, name) for name, q in pending.items() if q]
-    if not heads:
-        return None
-    _, name = min(heads)
-    q = pending[name]
-    take, k = [], 0
-    for r in q:
-        if k + r.k > max_k:
-            break
-        if footprint(name, k + r.k) > free_bytes:
-            break
-        take.append(r)
-        k += r.k
-    if not take:
-        return None
-    return name, take
 
 
 def poisson_trace(seed: int, rate_per_s: float, count: int, graphs, sources_of, k_max: int = 64):
@@ -91,100 +69,109 @@ def poisson_trace(seed: int, rate_per_s: float, count: int, graphs, sources_of, 
 
 
 class Server:
-    """Runs request traces against resident graphs (name -> paper_2512_21967_amd.Graph)."""
+    """Feeds request traces to a device server over resident graphs
+    (name -> paper_2512_21967_amd.Graph).  `device_server` may replace the libblest
+    server by any object with submit/poll/release (host-side tests)."""
 
-    def __init__(self, graphs: dict, hbm_budget: int, streams: int = 2, max_k: int = 64):
-        import torch
-        self.torch = torch
+    def __init__(self, graphs: dict, hbm_budget: int, idle_ms: int = 20, device_server=None, alloc=None):
         self.graphs = graphs
+        self.names = list(graphs)
+        self.index = {name: i for i, name in enumerate(self.names)}
         self.budget = int(hbm_budget)
-        self.max_k = max_k
-        self.streams = [torch.cuda.Stream() for _ in range(streams)]
         for name, g in graphs.items():
-            if g.footprint(1) > self.budget:
-                raise ValueError(f"graph {name}: a single source needs more than the HBM budget")
+            if self.footprint(name, 1) > self.budget:
+                raise ValueError(f"graph {name}: one source's output needs more than the HBM budget")
+        if device_server is None:
+            from . import DeviceServer
+            device_server = DeviceServer([graphs[n] for n in self.names], self.budget, idle_ms)
+        self.dev = device_server
+        self.alloc = alloc if alloc is not None else self._torch_alloc
+        self.outstanding = 0
+        self.peak_bytes = 0
+
+    def _torch_alloc(self, k, n):
+        import torch
+        return torch.empty((k, n), dtype=torch.int32, device=torch.device("cuda", self.graphs[self.names[0]].device))
 
     def footprint(self, graph: str, k: int) -> int:
-        return self.graphs[graph].footprint(k)
+        """Output bytes a request of k sources holds until it is released."""
+        return 4 * int(k) * int(self.graphs[graph].n)
 
-    def _launch(self, name, reqs, stream, batch_id):
-        torch = self.torch
-        g = self.graphs[name]
-        src = np.concatenate([r.sources for r in reqs]).astype(np.uint32)
-        with torch.cuda.stream(stream):
-            if src.size == 1:
-                out = torch.empty((1, g.n), dtype=torch.int32, device="cuda")
-                g.bfs(int(src[0]), levels=out.view(-1), stream=stream)
-            else:
-                out = torch.empty((src.size, g.n), dtype=torch.int32, device="cuda")
-                g.bfs_multi(src, levels=out, stream=stream)
-            done = torch.cuda.Event(enable_timing=True)
-            done.record(stream)
-        row = 0
-        for r in reqs:
-            r.levels = out[row:row + r.k]
-            r.batch_id = batch_id
-            row += r.k
-        return done
+    def release(self, r: Request):
+        if r.released or r.ticket is None:
+            return
+        self.dev.release(r.ticket)
+        self.outstanding -= self.footprint(r.graph, r.k)
+        r.released = True
 
-    def run(self, trace, realtime: bool = True):
+    def run(self, trace, realtime: bool = True, keep: bool = True, on_done=None, poll_sleep: float = 20e-6):
         """Replays `trace` [(t_arrival, graph, sources)] and returns the requests.
-        realtime=False submits everything at t = 0 (a closed-loop stress test)."""
-        torch = self.torch
-        torch.cuda.synchronize()
-        ref = torch.cuda.Event(enable_timing=True)
-        ref.record(torch.cuda.current_stream())
-        torch.cuda.synchronize()
+        realtime=False makes every request arrive at t = 0 (a closed-loop stress
+        test).  keep=False releases each request (and drops its output) right after
+        on_done(request) returns."""
         t0 = time.perf_counter()
         reqs = [Request(i, g, np.asarray(s, np.uint32), t0 + (t if realtime else 0.0)) for i, (t, g, s) in
                 enumerate(trace)]
         arrivals = collections.deque(reqs)
-        pending = {name: collections.deque() for name in self.graphs}
-        inflight = []  # (done_event, reqs, bytes, stream)
-        free_streams = list(self.streams)
-        used = 0
-        batch_id = 0
-        self.peak_bytes = 0
-        while arrivals or inflight or any(pending.values()):
+        waiting = collections.deque()
+        inflight = {}
+        while arrivals or waiting or inflight:
             now = time.perf_counter()
             while arrivals and arrivals[0].arrival <= now:
-                r = arrivals.popleft()
-                pending[r.graph].append(r)
-            still = []
-            for ev, rs, nbytes, st in inflight:
-                if ev.query():
-                    done_at = t0 + ref.elapsed_time(ev) / 1000.0
-                    for r in rs:
-                        r.done_at = done_at
-                    used -= nbytes
-                    free_streams.append(st)
-                else:
-                    still.append((ev, rs, nbytes, st))
-            inflight = still
-            launched = False
-            while free_streams:
-                plan = plan_batch(pending, self.budget - used, self.footprint, self.max_k)
-                if plan is None:
+                waiting.append(arrivals.popleft())
+            progressed = False
+            # oldest first; the head waits until its output fits the budget
+            while waiting:
+                r = waiting[0]
+                nbytes = self.footprint(r.graph, r.k)
+                if self.outstanding + nbytes > self.budget:
                     break
-                name, take = plan
-                for r in take:
-                    pending[name].popleft()
-                k = sum(r.k for r in take)
-                nbytes = self.footprint(name, k)
-                st = free_streams.pop()
-                ev = self._launch(name, take, st, batch_id)
-                batch_id += 1
-                used += nbytes
-                self.peak_bytes = max(self.peak_bytes, used)
-                inflight.append((ev, take, nbytes, st))
-                launched = True
-            if not launched and not arrivals and not any(pending.values()) and inflight:
-                inflight[0][0].synchronize()
-            elif not launched:
-                time.sleep(20e-6)
-        torch.cuda.synchronize()
-        self.batches = batch_id
+                out = self.alloc(r.k, self.graphs[r.graph].n)
+                t = self.dev.submit(self.index[r.graph], r.sources, out)
+                if t is None:  # the device's ring is full: wait for releases
+                    break
+                waiting.popleft()
+                r.ticket, r.levels, r.submitted_at = t, out, time.perf_counter()
+                self.outstanding += nbytes
+                self.peak_bytes = max(self.peak_bytes, self.outstanding)
+                inflight[t] = r
+                progressed = True
+            for t in list(inflight):
+                state, depth, a, d = self.dev.poll(t)
+                if state != 2:
+                    continue
+                r = inflight.pop(t)
+                r.done_at = time.perf_counter()
+                r.depth, r.admit_iter, r.done_iter = depth, a, d
+                progressed = True
+                if on_done is not None:
+                    on_done(r)
+                if not keep:
+                    self.release(r)
+                    r.levels = None
+            if keep and waiting and not inflight and not progressed and \
+                    self.outstanding + self.footprint(waiting[0].graph, waiting[0].k) > self.budget:
+                raise RuntimeError("budget held by kept requests: release them or use keep=False")
+            if not progressed:
+                time.sleep(poll_sleep)
         return reqs
+
+    def close(self):
+        if hasattr(self.dev, "close"):
+            self.dev.close()
+
+
+def overlapping_pairs(reqs) -> int:
+    """Pairs of requests that were on the device at once: admitted before the
+    other finished, in server iterations."""
+    iv = sorted((r.admit_iter, r.done_iter) for r in reqs if r.done_at is not None)
+    count = 0
+    for i, (a, d) in enumerate(iv):
+        for a2, d2 in iv[i + 1:]:
+            if a2 >= d:
+                break
+            count += 1
+    return count
 
 
 def summarize(reqs, edges_of=None):

@@ -73,7 +73,7 @@ def test_graph_validation_errors():
     assert L.blest_build(1, 0, None, None, ctypes.byref(o), ctypes.byref(h)) == 1
     assert L.blest_build(1, 0, blest._p32(rp), blest._p32(col), ctypes.byref(o), None) == 1
     for field, bad in (("sigma", 12), ("slots", 3), ("window", 12), ("reorder", 9), ("update", -1), ("block", 100),
-                       ("group", 3), ("blocks_per_cu", 2), ("ranges", 3), ("ranges", 64)):
+                       ("group", 3), ("blocks_per_cu", 3), ("ranges", 3), ("ranges", 64)):
         o = blest.default_options()
         o.device = -1
         setattr(o, field, bad)

@@ -119,11 +119,20 @@ def test_repeated_runs_identical():
 
 
 def test_launch_shapes():
+    """Workgroup shapes, including one asking for two 1024-thread workgroups per CU:
+    every persistent kernel here allocates more than 96 scalar registers (at most 7
+    wavefronts per SIMD), so that request is clamped to one workgroup per CU."""
     gr = inputs.rmat_workload(12, 16, seed=2, permute_seed=7)
     srcs = inputs.sources(gr, seed=5, k=2)
-    for block, per_cu in ((64, 1), (256, 1), (1024, 1), (256, 4), (512, 2)):
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for block, per_cu in ((64, 1), (256, 1), (1024, 1), (256, 4), (512, 2), (1024, 2)):
         for update in ("eager", "lazy"):
             g = blest.Graph(gr, update=update, reorder="none", block=block, blocks_per_cu=per_cu)
+            st = g.stats()
+            print(f"shape {block}x{per_cu} {update}: vgprs {st['kernel_vgprs']} runtime "
+                  f"{st['blocks_per_cu_runtime']} own {st['blocks_per_cu_own']} grid {st['grid']}", flush=True)
+            assert st["grid"] == cus * min(per_cu, st["blocks_per_cu_own"], st["blocks_per_cu_runtime"])
+            assert st["blocks_per_cu_own"] * block <= 7 * 4 * 64
             check_sources(gr, g, srcs)
 
 
