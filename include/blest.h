@@ -146,6 +146,24 @@ blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, cons
 blest_status blest_bfs(blest_handle h, uint32_t source, int32_t* levels_out, int32_t* parents_out,
                        void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): blest_bfs without the
+ * parents output, whose per-call state (visited bits, reached bytes, frontier
+ * bitmaps, queues, control block) lives in a static device array of
+ * BLEST_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on
+ * until the process ends, instead of the per-stream workspace that blest_bfs
+ * allocates on a stream's first call.  The call allocates nothing (no hipMalloc,
+ * hipFree or event creation) and needs n/8 + n + 3n/8 + 16 * num_vss bytes (each
+ * part rounded up to 256) plus a 2 KiB control block; a graph needing more
+ * returns BLEST_ERR_BUDGET before anything is enqueued.  Every call on a device
+ * shares that device's scratch, which keeps the last call's contents; the call
+ * clears what must start at zero.  The library orders every persistent launch on
+ * a device behind the previous one, so calls from several streams do not run at
+ * once; work that bypassed that order and used the same scratch would race.
+ * Arguments, levels_out and errors as for blest_bfs. */
+#define BLEST_NOALLOC_SCRATCH_BYTES (64u << 20)
+blest_status blest_bfs_noalloc(blest_handle h, uint32_t source, int32_t* levels_out, void* stream);
+
 /* k-source BFS in one launch: sources is a HOST array of k vertex IDs
  * (1 <= k <= 64, repeats allowed); levels_out is DEVICE int32[k * n], row j
  * (levels_out[j*n .. j*n+n-1]) belongs to sources[j].  The frontiers form an

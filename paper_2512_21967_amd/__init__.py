@@ -26,7 +26,7 @@ LDS_OFF = 0xFFFFFFFF
 EXPORT = {"new_id": (0, np.uint32), "real_ptrs": (1, np.uint32), "virtual_to_real": (2, np.uint32),
           "vss_begin": (3, np.uint32), "row_ids": (4, np.uint32), "masks": (5, np.uint8),
           "vss_range": (6, np.uint8), "order_id": (7, np.uint32)}
-EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_bfs_multi",
+EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_bfs_noalloc", "blest_bfs_multi",
                     "blest_bfs_many",
                     "blest_batch_create", "blest_batch_run", "blest_batch_destroy", "blest_server_create",
                     "blest_server_submit", "blest_server_poll", "blest_server_release", "blest_server_stats",
@@ -89,6 +89,8 @@ def lib():
     L.blest_build.restype = ctypes.c_int
     L.blest_bfs.argtypes = [vp, u32, vp, vp, vp]
     L.blest_bfs.restype = ctypes.c_int
+    L.blest_bfs_noalloc.argtypes = [vp, u32, vp, vp]
+    L.blest_bfs_noalloc.restype = ctypes.c_int
     L.blest_bfs_multi.argtypes = [vp, p32, u32, vp, vp]
     L.blest_bfs_multi.restype = ctypes.c_int
     L.blest_bfs_many.argtypes = [ctypes.POINTER(vp), p32, u32, ctypes.POINTER(vp), vp]
@@ -226,6 +228,15 @@ class Graph:
                                             ctypes.c_void_p(par.data_ptr() if par is not None else 0),
                                             _stream_ptr(stream)))
         return (levels, par) if par is not None else levels
+
+    def bfs_noalloc(self, source: int, levels, stream=None):
+        """Levels from `source` into the caller's int32 CUDA tensor [n] through
+        blest_bfs_noalloc, which allocates nothing (its state lives in the
+        library's static device scratch).  Asynchronous on `stream`."""
+        _require_int32_cuda(levels, self.n, "levels")
+        _check("blest_bfs_noalloc", lib().blest_bfs_noalloc(self.handle, int(source),
+                                                            ctypes.c_void_p(levels.data_ptr()), _stream_ptr(stream)))
+        return levels
 
     def bfs_multi(self, sources, levels=None, stream=None):
         """Levels of k <= 64 sources in one launch: int32 CUDA tensor [k, n]."""

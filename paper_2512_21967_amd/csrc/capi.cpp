@@ -581,6 +581,48 @@ blest_status blest_bfs(blest_handle h, uint32_t source, int32_t* levels_out, int
   }
 }
 
+blest_status blest_bfs_noalloc(blest_handle h, uint32_t source, int32_t* levels_out, void* stream) {
+  if (!h || !levels_out) return BLEST_ERR_INVALID_ARGUMENT;
+  if (source >= h->n) return BLEST_ERR_INVALID_ARGUMENT;
+  // the per-call state, carved out of the static scratch in 256-byte-aligned parts
+  const uint64_t nw = h->n_words();
+  const uint64_t parts[5] = {4 * nw, 32 * nw, 12 * nw, 16ull * std::max<uint32_t>(h->bvss.num_vss, 1),
+                             4ull * kCtrlWords};
+  uint64_t off[5], need = 0;
+  for (int i = 0; i < 5; ++i) {
+    off[i] = need;
+    need += (parts[i] + 255) / 256 * 256;
+  }
+  if (need > BLEST_NOALLOC_SCRATCH_BYTES) return BLEST_ERR_BUDGET;
+  if (!h->on_device) return BLEST_ERR_NO_DEVICE;
+  try {
+    if (hipSetDevice(h->device) != hipSuccess) return BLEST_ERR_DEVICE;
+    void* base = nullptr;
+    if (noalloc_scratch(h->device, &base) != hipSuccess || !base) return BLEST_ERR_DEVICE;
+    char* sb = static_cast<char*>(base);
+    BfsParams p = base_params(h);
+    p.vis = reinterpret_cast<uint32_t*>(sb + off[0]);
+    p.mark = reinterpret_cast<uint8_t*>(sb + off[1]);
+    p.front = reinterpret_cast<uint32_t*>(sb + off[2]);
+    p.queue = reinterpret_cast<uint32_t*>(sb + off[3]);
+    p.ctrl = reinterpret_cast<uint32_t*>(sb + off[4]);
+    p.levels = levels_out;
+    p.src = h->new_id[source];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // The scratch keeps the last call's contents: the barrier counters and queue
+    // lengths are cleared by a fill kernel, ordered with the BFS launch behind the
+    // previous persistent launch on the device.
+    hipError_t e = serial_launch(h->device, s, [&] {
+      hipError_t z = launch_zero_words(p.ctrl, kCtrlWords, s);
+      if (z != hipSuccess) return z;
+      return launch_bfs(p, h->bvss.sigma, h->bvss.slots, h->lazy, h->opt.group, h->grid, h->block, s);
+    });
+    return e == hipSuccess ? BLEST_OK : BLEST_ERR_DEVICE;
+  } catch (...) {
+    return BLEST_ERR_INTERNAL;
+  }
+}
+
 blest_status blest_bfs_multi(blest_handle h, const uint32_t* sources, uint32_t k, int32_t* levels_out,
                              void* stream) {
   if (!h || !sources || !levels_out || k == 0 || k > 64) return BLEST_ERR_INVALID_ARGUMENT;

@@ -29,7 +29,9 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <mutex>
 
+#include "../../include/blest.h"
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -765,7 +767,39 @@ const void* sym_slots(uint32_t slots, bool lazy, uint32_t group, bool lds) {
   }
 }
 
+__global__ void zero_words(uint32_t* __restrict__ p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
 }  // namespace
+
+// Scratch of the allocation-free single-source entry point (blest_bfs_noalloc):
+// visited bits, reached bytes, frontier bitmaps, queues and the control block of
+// one call, carved out at 256-byte boundaries.  Each device holds its own copy
+// for the life of the process.  In host code this name is only a stand-in for
+// the symbol: kernels get the address that hipGetSymbolAddress reports for the
+// current device (noalloc_scratch), never the name itself.
+static __device__ __align__(256) unsigned char scratch[BLEST_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(int device, void** ptr) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    void* a = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = a;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
+
+hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t stream) {
+  hipLaunchKernelGGL(zero_words, dim3(1), dim3(512), 0, stream, p, n);
+  return hipGetLastError();
+}
 
 const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, bool lds) {
   switch (sigma) {

@@ -198,4 +198,11 @@ hipError_t launch_level_stats(const int32_t* levels, uint32_t k, uint32_t n, uns
 hipError_t launch_parents(const BfsParams& p, uint32_t sigma, const int32_t* levels, int32_t* parents,
                           hipStream_t stream);
 
+// Device address of the allocation-free entry point's static scratch array on
+// `device` (which must be the current device); looked up once per device.
+hipError_t noalloc_scratch(int device, void** ptr);
+
+// Zeroes n 32-bit words at p with one small ordinary launch on `stream`.
+hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t stream);
+
 }  // namespace blest
