@@ -56,6 +56,42 @@ def roofline(bytes_per_launch, mean_launch_s, key):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key)}
 
 
+def tuned_options(gr, k, args):
+    """The autotuner's stored choice for this graph's class and size (None when
+    absent, or when --no-tuned or an explicit --update was given)."""
+    from paper_2512_21967_amd import autotune
+    key, opts = autotune.lookup(gr, k)
+    if args.no_tuned or getattr(args, "update", "auto") != "auto" or not opts:
+        return key, None
+    if k > 1:  # the k-source kernel takes the layout only
+        opts = {"sigma": opts["sigma"], "slots": opts["slots"]}
+    return key, opts
+
+
+def barrier_count(g, st, lv):
+    """Grid barriers of one single-source BFS with levels `lv`: one after the
+    initialisation, then per iteration (max level + 1 of them) one for an eager
+    level and two for a lazy one; the adaptive scheme runs iteration i lazily iff
+    its queue (the VSSs of the slice sets holding a vertex of level i - 1) has at
+    least eager_max entries."""
+    import numpy as np
+    iters = int(lv.max()) + 1
+    mode = st["update_used"]
+    if mode == "eager":
+        return 1 + iters
+    if mode == "lazy":
+        return 1 + 2 * iters
+    sig = st["sigma"]
+    rp = g.export("real_ptrs").astype(np.int64)
+    lv_new = np.empty_like(lv)
+    lv_new[g.export("new_id")] = lv
+    v = np.flatnonzero(lv_new >= 0)
+    pairs = np.unique(lv_new[v].astype(np.int64) * (len(rp) - 1) + v // sig)
+    lvl, sets = pairs // (len(rp) - 1), pairs % (len(rp) - 1)
+    queued = np.bincount(lvl, weights=(rp[sets + 1] - rp[sets]).astype(np.float64), minlength=iters)
+    return 1 + iters + int(np.sum(queued[:iters] >= st["eager_max"]))
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -158,8 +194,14 @@ def run_single(args):
     gr, gopts, sources, desc = single_workload(args.workload)
     log(f"[bench] graph {gr.name}: n={gr.n} arcs={gr.nnz} ({time.time() - t0:.1f}s)")
     t0 = time.time()
-    g = blest.Graph(gr, update=args.update, device=0, ranges=args.ranges, **gopts)
+    tuned_key, tuned = tuned_options(gr, 1, args)
+    opts = dict(gopts, update=args.update)
+    if tuned:
+        opts.update(tuned)
+    g = blest.Graph(gr, device=0, ranges=args.ranges, **opts)
     st = g.stats()
+    if tuned:
+        log(f"[bench] tuned choice for {tuned_key}: {tuned}")
     log(f"[bench] build {time.time() - t0:.1f}s: reorder {st['reorder_used']} ({st['reorder_seconds']:.1f}s), "
         f"update {st['update_used']}, compression {st['compression']:.3f}, VSS {st['num_vss']}, "
         f"ranges {st['nranges']}, slices {st['num_slices']}, U_div {st['u_div_paper']:.0f}, "
@@ -197,6 +239,8 @@ def run_single(args):
     model = {}
     bad = []
 
+    lat_levels = [gpu_levels[i] for i in range(min(4, len(sources)))]
+
     def check(i, want):
         if not np.array_equal(gpu_levels[i], want):
             bad.append(int(sources[i]))
@@ -225,14 +269,54 @@ def run_single(args):
               "sigma": st["sigma"], "tau": st["tau"], "ranges": st["nranges"], "grid": st["grid"],
               "block": st["block"], "compression": round(st["compression"], 4),
               "ms_per_bfs_mean": round(float(ms.mean()), 4), "ms_per_bfs_median": round(float(np.median(ms)), 4),
-              "model_bytes_per_bfs": int(mb.mean()), "model_bytes_from": "oracle levels" if checked else "gpu levels"}
-    extra = {"parity": parity}
+              "model_bytes_per_bfs": int(mb.mean()), "model_bytes_from": "oracle levels" if checked else "gpu levels",
+              "eager_max": st["eager_max"] if st["update_used"] == "adaptive" else None, "group": opts.get("group", 2),
+              "slots": st["tau"] // 64, "tuned": {"key": tuned_key, "options": tuned} if tuned else None}
+    # the latency bound: every level costs at least its grid barriers
+    t_bar = blest.barrier_seconds(0, st["block"])
+    nbar = np.array([barrier_count(g, st, gpu_or_none) for gpu_or_none in lat_levels], dtype=np.float64)
+    t_lat = nbar.mean() * t_bar
+    t_hbm = mb.mean() / (HBM_PEAK_GBS * 1e9)
+    bound = max(t_lat, t_hbm)
+    extra = {"parity": parity,
+             "latency_bound": {"t_barrier_us": round(t_bar * 1e6, 3), "barriers_per_bfs": round(float(nbar.mean()), 1),
+                               "t_lat_ms": round(t_lat * 1e3, 4), "t_hbm_ms": round(t_hbm * 1e3, 4),
+                               "bound": "latency" if t_lat > t_hbm else "hbm",
+                               "frac_of_bound": round(bound / (ms.mean() / 1000.0), 4)}}
+    log(f"[bench] bounds: {nbar.mean():.0f} barriers x {t_bar * 1e6:.2f} us = {t_lat * 1e3:.3f} ms, "
+        f"HBM {t_hbm * 1e3:.3f} ms; measured {ms.mean():.3f} ms")
     if args.workload == "rmat22" and not args.no_batched:
         extra["batched"] = batched_leg(args)
+    if args.workload == "rmat22" and not args.no_serving:
+        extra["serving"] = serving_leg(args, gr, g)
     g.close()
     line(gteps, args, wall * 1000 / args.steps, "u32", config, roof, cpu, extra)
     if bad or ("batched" in extra and "MISMATCH" in extra["batched"]["parity"]):
         sys.exit(1)
+
+
+def serving_leg(args, gr22, g22):
+    """The p99 part of the metric: the serving workload (resident R-MAT S18, R-MAT S22
+    - the headline's build - and grid 2048^2) at offered load rho = 0.5, on a
+    shorter trace than the full sweep of --workload serve."""
+    import paper_2512_21967_amd as blest
+    import inputs
+    graphs = {"rmat18": inputs.rmat_workload(18, 16, seed=11, permute_seed=12), "rmat22": gr22,
+              "grid2048": inputs.grid_workload(2048, 0.9, seed=3, permute_seed=4)}
+    # one server needs one layout: the other graphs take the headline build's
+    st22 = g22.stats()
+    lay = {"sigma": st22["sigma"], "slots": st22["tau"] // 64}
+    handles = {"rmat18": blest.Graph(graphs["rmat18"], device=0, **lay), "rmat22": g22,
+               "grid2048": blest.Graph(graphs["grid2048"], device=0, **lay)}
+    service, sweep, st = serve_sweep(handles, graphs, (0.5,), args.serve_leg_requests, 16 << 30)
+    handles["rmat18"].close()
+    handles["grid2048"].close()
+    s = sweep[0]
+    return {"workload": "Poisson requests (k=1 w.p. 1/2 else U{1..64}) over resident R-MAT S18, R-MAT S22, grid "
+                        "2048^2, continuous batching; full rate sweep: --workload serve",
+            "rho": 0.5, "requests": s["requests"], "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"],
+            "gteps": s["gteps"], "lone_service_ms": round(service * 1000, 3),
+            "overlapping_pairs": s["overlapping_pairs"]}
 
 
 def batched_leg(args):
@@ -246,7 +330,8 @@ def batched_leg(args):
 
     gr = inputs.rmat_workload(20, 16, seed=1)
     srcs = inputs.sources(gr, seed=7, k=64, distinct=True)
-    g = blest.Graph(gr, reorder="none", device=0)
+    tuned_key, tuned = tuned_options(gr, 64, args)
+    g = blest.Graph(gr, reorder="none", device=0, **(tuned or {}))
     deg = gr.degrees()
     stream = torch.cuda.current_stream()
     out = torch.empty((64, gr.n), dtype=torch.int32, device="cuda")
@@ -303,7 +388,7 @@ def batched_leg(args):
             "gteps": round(gteps, 3), "ms_per_launch": round(ms, 4), "sequential_gteps": round(seq_gteps, 3),
             "sequential_ms": round(seq * 1000, 3), "speedup_vs_sequential": round(gteps / seq_gteps, 2),
             "model_bytes_per_launch": int(model), "hbm_frac": round(model / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
-            "parity": parity, "cpu_baseline": cpu}
+            "parity": parity, "cpu_baseline": cpu, "tuned": {"key": tuned_key, "options": tuned} if tuned else None}
 
 
 # ---------------------------------------------------------------------------
@@ -381,7 +466,8 @@ def run_multi(args):
 
     gr = inputs.rmat_workload(20, 16, seed=1)
     srcs = inputs.sources(gr, seed=7, k=64, distinct=True)
-    g = blest.Graph(gr, reorder="none", device=0)
+    tuned_key, tuned = tuned_options(gr, 64, args)
+    g = blest.Graph(gr, reorder="none", device=0, **(tuned or {}))
     deg = gr.degrees()
     out = torch.empty((64, gr.n), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -448,7 +534,7 @@ def run_multi(args):
     config = {"workload": "R-MAT scale 20 ef 16, generator labels, 64 distinct sources in one k-source launch",
               "n": gr.n, "arcs": int(gr.nnz), "sources": 64, "sequential_single_source_gteps": round(seq_gteps, 3),
               "speedup_vs_sequential": round(gteps / seq_gteps, 2), "ms_per_launch_mean": round(float(ms.mean()), 4),
-              "level_stats_ms": round(stats_ms, 4),
+              "level_stats_ms": round(stats_ms, 4), "tuned": {"key": tuned_key, "options": tuned} if tuned else None,
               "level_stats_one_pass_gbs": round(4.0 * 64 * gr.n / (stats_ms / 1000.0) / 1e9, 1)}
     line(gteps, args, wall * 1000 / args.steps, "u64", config, roof, cpu, {"parity": parity})
     g.close()
@@ -547,50 +633,101 @@ def run_many(args):
 # serving
 # ---------------------------------------------------------------------------
 
-def run_serve(args):
-    import numpy as np
-    import torch
-    import inputs
-    import paper_2512_21967_amd as blest
-    from paper_2512_21967_amd.serve import Server, poisson_trace, summarize
+SERVE_RHOS = (0.1, 0.25, 0.5, 0.75, 0.9, 1.1)
 
-    t0 = time.time()
-    graphs = {"rmat18": inputs.rmat_workload(18, 16, seed=11, permute_seed=12),
-              "rmat22": inputs.rmat_workload(22, 16, seed=1, permute_seed=2),
-              "grid2048": inputs.grid_workload(2048, 0.9, seed=3, permute_seed=4)}
-    handles = {k: blest.Graph(v, device=0) for k, v in graphs.items()}
-    degs = {k: v.degrees() for k, v in graphs.items()}
-    log(f"[bench] resident graphs built ({time.time() - t0:.1f}s): " +
+
+def serve_graphs():
+    import inputs
+    return {"rmat18": inputs.rmat_workload(18, 16, seed=11, permute_seed=12),
+            "rmat22": inputs.rmat_workload(22, 16, seed=1, permute_seed=2),
+            "grid2048": inputs.grid_workload(2048, 0.9, seed=3, permute_seed=4)}
+
+
+def component_edges(gr):
+    """(component label per vertex, undirected edges per component) of a symmetric
+    graph: a BFS from s traverses exactly the edges of s's component."""
+    import numpy as np
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    a = sp.csr_matrix((np.ones(gr.nnz, np.int8), gr.col.astype(np.int32), gr.row_ptr.astype(np.int64)),
+                      shape=(gr.n, gr.n))
+    _, lab = connected_components(a, directed=False)
+    return lab, np.bincount(lab, weights=gr.degrees().astype(np.float64)) / 2.0
+
+
+def serve_sweep(handles, graphs, rhos, nreq, budget, log_prefix="[bench]"):
+    """Lone service time (closed loop, one request at a time), then one Poisson trace
+    of `nreq` requests per offered load rho = rate * lone service time."""
+    import numpy as np
+    import inputs
+    from paper_2512_21967_amd.serve import Server, overlapping_pairs, poisson_trace, summarize
+
+    names = list(graphs)
+    comp = {k: component_edges(v) for k, v in graphs.items()}
+    edges_of = lambda r: float(sum(comp[r.graph][1][comp[r.graph][0][int(s)]] for s in r.sources))
+    src_of = lambda g, seed, k: inputs.sources(graphs[g], seed=seed, k=k)
+    srv = Server(handles, budget)
+    lone = []
+    for t, gname, s in poisson_trace(99, 1.0, 40, names, src_of):
+        lone.append(srv.run([(0.0, gname, s)], realtime=False, keep=False)[0].latency)
+    service = float(np.mean(lone[8:]))
+    log(f"{log_prefix} mean lone service time {service * 1000:.2f} ms")
+    sweep = []
+    for rho in rhos:
+        trace = poisson_trace(int(rho * 1000) + 17, rho / service, nreq, names, src_of)
+        reqs = srv.run(trace, keep=False)
+        s = summarize(reqs, edges_of)
+        wait = np.array([r.submitted_at - r.arrival for r in reqs]) * 1000.0
+        s.update({"rho": rho, "rate_per_s": round(rho / service, 2), "p50_host_wait_ms": float(np.percentile(wait, 50)),
+                  "p99_host_wait_ms": float(np.percentile(wait, 99)),
+                  "budget_waits": int(np.sum(wait > 1.0)), "rejected": 0,
+                  "overlapping_pairs": overlapping_pairs(reqs), "peak_output_bytes": srv.peak_bytes,
+                  "per_graph_p99_ms": {g: float(np.percentile([r.latency * 1000 for r in reqs if r.graph == g], 99))
+                                       for g in names if any(r.graph == g for r in reqs)}})
+        for k in ("p50_ms", "p99_ms", "mean_ms", "gteps", "p50_host_wait_ms", "p99_host_wait_ms"):
+            s[k] = round(s[k], 4)
+        sweep.append(s)
+        log(f"{log_prefix} rho {rho}: p50 {s['p50_ms']:.2f} ms, p99 {s['p99_ms']:.2f} ms, {s['gteps']:.2f} GTEPS, "
+            f"{s['requests']} requests, {s['overlapping_pairs']} overlapping pairs")
+    st = srv.dev.stats()
+    srv.close()
+    return service, sweep, st
+
+
+def run_serve(args):
+    import time as _t
+    import paper_2512_21967_amd as blest
+
+    t0 = _t.time()
+    graphs = serve_graphs()
+    # the autotuner's k-source layout when every graph has one and they agree (one
+    # server needs one layout); the defaults otherwise
+    from paper_2512_21967_amd import autotune
+    found = [autotune.lookup(v, 64)[1] for v in graphs.values()]
+    lays = {(o["sigma"], o["slots"]) for o in found if o}
+    lay = {}
+    if all(found) and len(lays) == 1 and not args.no_tuned:
+        sg, sl = lays.pop()
+        lay = {"sigma": sg, "slots": sl}
+    handles = {k: blest.Graph(v, device=0, **lay) for k, v in graphs.items()}
+    log(f"[bench] resident graphs built ({_t.time() - t0:.1f}s): " +
         ", ".join(f"{k} {h.stats()['reorder_used']}/{h.stats()['update_used']}" for k, h in handles.items()))
     budget = 16 << 30
-    names = list(graphs)
-    src_of = lambda g, seed, k: inputs.sources(graphs[g], seed=seed, k=k)
-    srv = Server(handles, budget, streams=2)
-    # mean service time of a lone request (closed loop, one at a time)
-    probe = poisson_trace(99, 1.0, 24, names, src_of)
-    lone = []
-    for t, gname, s in probe:
-        r = srv.run([(0.0, gname, s)], realtime=False)[0]
-        lone.append(r.latency)
-    service = float(np.mean(lone[5:]))
-    log(f"[bench] mean lone service time {service * 1000:.2f} ms")
-    edges_of = lambda r: sum(float(degs[r.graph][row >= 0].sum()) / 2.0 for row in r.levels.cpu().numpy())
-    sweep = []
-    for rho in (0.25, 0.5, 0.9):
-        trace = poisson_trace(int(rho * 1000), rho / service, args.serve_requests, names, src_of)
-        reqs = srv.run(trace)
-        s = summarize(reqs, edges_of)
-        s.update({"rho": rho, "rate_per_s": round(rho / service, 2), "batches": srv.batches,
-                  "peak_bytes": srv.peak_bytes})
-        sweep.append(s)
-        log(f"[bench] rho {rho}: p50 {s['p50_ms']:.2f} ms, p99 {s['p99_ms']:.2f} ms, {s['gteps']:.2f} GTEPS, "
-            f"{s['batches']} batches for {s['requests']} requests")
+    rhos = tuple(float(x) for x in args.serve_rhos.split(",")) if args.serve_rhos else SERVE_RHOS
+    service, sweep, st = serve_sweep(handles, graphs, rhos, args.serve_requests, budget)
     best = max(s["gteps"] for s in sweep)
     config = {"workload": "Poisson requests (k=1 w.p. 1/2 else U{1..64}) over resident R-MAT S18, R-MAT S22, "
-                          "grid 2048^2 p=0.9; HBM budget 16 GiB", "requests_per_rate": args.serve_requests,
-              "lone_service_ms": round(service * 1000, 3)}
-    line(best, argparse.Namespace(steps=len(sweep), warmup=1), 0.0, "u64", config, None, None,
-         {"serving": sweep, "p99_ms_at_rho_0.5": next(s["p99_ms"] for s in sweep if s["rho"] == 0.5)})
+                          "grid 2048^2 p=0.9, continuous batching in one persistent server launch; HBM budget "
+                          "16 GiB for outputs", "requests_per_rate": args.serve_requests,
+              "lone_service_ms": round(service * 1000, 3), "server_launches": st["launches"],
+              "server_resident_bytes": st["resident_bytes"]}
+    extra = {"serving": sweep}
+    half = [s for s in sweep if s["rho"] == 0.5]
+    if half:
+        extra["p99_ms_at_rho_0.5"] = half[0]["p99_ms"]
+    line(best, argparse.Namespace(steps=len(sweep), warmup=1), 0.0, "u64", config, None, None, extra)
+    for h in handles.values():
+        h.close()
 
 
 # ---------------------------------------------------------------------------
@@ -616,12 +753,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22",
                     choices=["rmat22", "rmat16", "grid4096", "rmat20x64", "many256", "serve", "wsweep"])
-    ap.add_argument("--update", default="auto", choices=["auto", "eager", "lazy"])
+    ap.add_argument("--update", default="auto", choices=["auto", "eager", "lazy", "adaptive"])
     ap.add_argument("--ranges", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=16)
-    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rhos", default="", help="comma-separated offered loads (default: the full sweep)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg of the default workload")
+    ap.add_argument("--serve-leg-requests", type=int, default=400)
+    ap.add_argument("--no-tuned", action="store_true", help="ignore the autotuner's stored choices")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the k-source leg of the default workload")
     args = ap.parse_args()

@@ -63,8 +63,11 @@ enum {
 
 /* Vertex-update schemes.  AUTO: lazy (Algorithm 3) iff the graph is social-like
  * and its update divergence exceeds 25,000 (Section 4, discussion of Table 3);
- * otherwise eager (Algorithm 2). */
-enum { BLEST_UPDATE_AUTO = 0, BLEST_UPDATE_EAGER = 1, BLEST_UPDATE_LAZY = 2 };
+ * otherwise eager (Algorithm 2).  ADAPTIVE chooses per level, on the device, from
+ * the level's queue length (the per-level policy the paper leaves to future work,
+ * Section 6): levels with fewer than eager_max queued VSSs claim eagerly (one grid
+ * barrier, no vertex sweep), others mark lazily and sweep. */
+enum { BLEST_UPDATE_AUTO = 0, BLEST_UPDATE_EAGER = 1, BLEST_UPDATE_LAZY = 2, BLEST_UPDATE_ADAPTIVE = 3 };
 
 typedef struct {
   uint32_t sigma;      /* slice width in columns: 8 (the paper's value), 16 or 32 */
@@ -89,6 +92,8 @@ typedef struct {
                           0 = auto (128, clamped to the device), 1..128, or BLEST_LDS_OFF.  The
                           cache holds the first C words (C a power of two) of every 64-word
                           chunk of the range, C as large as fits */
+  uint32_t eager_max;  /* BLEST_UPDATE_ADAPTIVE: levels with fewer queued VSSs run eagerly
+                          (0 = num_vss / 32) */
 } blest_options;
 
 #define BLEST_LDS_OFF 0xFFFFFFFFu
@@ -122,6 +127,7 @@ typedef struct {
   uint32_t blocks_per_cu_runtime; /* workgroups per CU the runtime's occupancy query allows */
   uint32_t blocks_per_cu_own;   /* workgroups per CU by the kernel's registers and LDS (gfx950 rules);
                                    the grid uses the smaller of the two and blocks_per_cu */
+  uint32_t eager_max;           /* adaptive threshold in effect (queued VSSs) */
 } blest_stats_t;
 
 /* Fills *opt with the defaults listed above. */
@@ -153,8 +159,9 @@ blest_status blest_bfs(blest_handle h, uint32_t source, int32_t* levels_out, int
  * BLEST_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on
  * until the process ends, instead of the per-stream workspace that blest_bfs
  * allocates on a stream's first call.  The call allocates nothing (no hipMalloc,
- * hipFree or event creation) and needs n/8 + n + 3n/8 + 16 * num_vss bytes (each
- * part rounded up to 256) plus a 2 KiB control block; a graph needing more
+ * hipFree or event creation) and needs n/8 + n + 3n/8 bytes plus 12, 16 or 24 bytes
+ * per VSS of queues (eager, lazy, adaptive scheme), each part rounded up to 256,
+ * plus a 2 KiB control block; a graph needing more
  * returns BLEST_ERR_BUDGET before anything is enqueued.  Every call on a device
  * shares that device's scratch, which keeps the last call's contents; the call
  * clears what must start at zero.  The library orders every persistent launch on
@@ -261,12 +268,13 @@ blest_status blest_server_stats(blest_server_handle s, blest_server_stats_t* out
 blest_status blest_server_destroy(blest_server_handle s, uint32_t timeout_ms);
 
 /* Changes the launch settings of a built handle without rebuilding it: update
- * scheme (BLEST_UPDATE_*), threads per workgroup, workgroups per compute unit and
- * VSS group depth, with the meanings (and 0 = default) of blest_options.  Used by
- * autotuning.  Must not be called while work on the handle is in flight.
+ * scheme (BLEST_UPDATE_*), threads per workgroup, workgroups per compute unit, VSS
+ * group depth and the adaptive scheme's eager_max, with the meanings (and 0 =
+ * default) of blest_options.  Used by autotuning.  Must not be called while work
+ * on the handle is in flight.
  * Errors: INVALID_ARGUMENT (bad values; the handle is left unchanged), DEVICE. */
-blest_status blest_configure(blest_handle h, int32_t update, uint32_t block, uint32_t blocks_per_cu,
-                             uint32_t group);
+blest_status blest_configure(blest_handle h, int32_t update, uint32_t block, uint32_t blocks_per_cu, uint32_t group,
+                             uint32_t eager_max);
 
 /* Structure statistics of a built handle (host-side, no device access). */
 blest_status blest_stats(blest_handle h, blest_stats_t* out);
@@ -314,13 +322,23 @@ blest_status blest_level_stats(int32_t device, const int32_t* levels, uint32_t k
  * sigma-bit chunk, or sigma 64-bit words when k > 1) and 8 bytes per VSS (queue
  * entry + VSS metadata); plus, for k = 1, the lazy scheme's per-level sweep of the
  * two n-bit visited bitmaps, the 4n-byte level initialisation and 4 bytes per
- * reached vertex (its level write); for k > 1, per
+ * reached vertex (its level write) (the sweep counted for the iterations the
+ * handle's scheme runs lazily: all, none, or, adaptive, those whose queue holds
+ * at least eager_max VSSs); for k > 1, per
  * iteration, a 25n-byte vertex sweep when the queue holds at least 1/16 of the
  * VSSs, else n state bytes plus 26 bytes per vertex changed in the iteration and 8
  * per vertex leaving the frontier; the 4kn-byte initialisation and 4 bytes per
  * reached (source, vertex) pair.  Lets a benchmark turn a measured time into GB/s.
  * Errors: INVALID_ARGUMENT. */
 blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k, uint64_t* bytes);
+
+/* Measures the grid barrier of the persistent launches (one workgroup of `block`
+ * threads per compute unit): a launch doing `rounds` barriers and nothing else,
+ * timed with HIP events after a warm-up run; *seconds_per_barrier = time /
+ * rounds.  For the latency bound of high-diameter graphs, where every level costs
+ * at least one barrier.  Synchronous; allocates a small control block.
+ * Errors: INVALID_ARGUMENT, NO_DEVICE, DEVICE. */
+blest_status blest_barrier_probe(int32_t device, uint32_t block, uint32_t rounds, double* seconds_per_barrier);
 
 /* Releases the handle and its device memory.  NULL is ignored.  Must not be called
  * while work using the handle is still pending on a stream. */

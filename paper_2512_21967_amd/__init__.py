@@ -20,7 +20,7 @@ BLEST_OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "invalid graph", 3: "too large", 4: "out of memory",
           5: "budget", 6: "device error", 7: "no device", 8: "internal error"}
 REORDER = {"auto": 0, "none": 1, "compression": 2, "bandwidth": 3}
-UPDATE = {"auto": 0, "eager": 1, "lazy": 2}
+UPDATE = {"auto": 0, "eager": 1, "lazy": 2, "adaptive": 3}
 HUBS = {"auto": 0, "off": 1, "on": 2}
 LDS_OFF = 0xFFFFFFFF
 EXPORT = {"new_id": (0, np.uint32), "real_ptrs": (1, np.uint32), "virtual_to_real": (2, np.uint32),
@@ -31,7 +31,8 @@ EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_
                     "blest_batch_create", "blest_batch_run", "blest_batch_destroy", "blest_server_create",
                     "blest_server_submit", "blest_server_poll", "blest_server_release", "blest_server_stats",
                     "blest_server_destroy", "blest_configure", "blest_stats", "blest_footprint", "blest_export",
-                    "blest_model_bytes", "blest_level_stats", "blest_destroy", "blest_status_string")
+                    "blest_model_bytes", "blest_level_stats", "blest_barrier_probe", "blest_destroy",
+                    "blest_status_string")
 
 
 class ServerStats(ctypes.Structure):
@@ -51,7 +52,7 @@ class Options(ctypes.Structure):
                 ("reorder", ctypes.c_int32), ("update", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("threads", ctypes.c_uint32), ("block", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("group", ctypes.c_uint32), ("ranges", ctypes.c_uint32), ("hubs", ctypes.c_uint32),
-                ("lds_kib", ctypes.c_uint32)]
+                ("lds_kib", ctypes.c_uint32), ("eager_max", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -66,7 +67,8 @@ class Stats(ctypes.Structure):
                 ("hubs_sorted", ctypes.c_int32), ("lds_bytes", ctypes.c_uint32),
                 ("lds_chunk_words", ctypes.c_uint32), ("hub_cpos", ctypes.c_uint32),
                 ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32), ("kernel_vgprs", ctypes.c_uint32),
-                ("blocks_per_cu_runtime", ctypes.c_uint32), ("blocks_per_cu_own", ctypes.c_uint32)]
+                ("blocks_per_cu_runtime", ctypes.c_uint32), ("blocks_per_cu_own", ctypes.c_uint32),
+                ("eager_max", ctypes.c_uint32)]
 
 
 _lib = None
@@ -113,7 +115,7 @@ def lib():
     L.blest_server_stats.restype = ctypes.c_int
     L.blest_server_destroy.argtypes = [vp, u32]
     L.blest_server_destroy.restype = ctypes.c_int
-    L.blest_configure.argtypes = [vp, i32, u32, u32, u32]
+    L.blest_configure.argtypes = [vp, i32, u32, u32, u32, u32]
     L.blest_configure.restype = ctypes.c_int
     L.blest_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.blest_stats.restype = ctypes.c_int
@@ -125,6 +127,8 @@ def lib():
     L.blest_model_bytes.restype = ctypes.c_int
     L.blest_level_stats.argtypes = [i32, vp, u32, u32, vp, vp, vp, vp, vp, vp]
     L.blest_level_stats.restype = ctypes.c_int
+    L.blest_barrier_probe.argtypes = [i32, u32, u32, ctypes.POINTER(ctypes.c_double)]
+    L.blest_barrier_probe.restype = ctypes.c_int
     L.blest_destroy.argtypes = [vp]
     L.blest_destroy.restype = None
     L.blest_status_string.argtypes = [ctypes.c_int]
@@ -170,13 +174,15 @@ class Graph:
     and exports work; BFS calls raise)."""
 
     def __init__(self, csr, *, sigma=8, slots=2, window=1 << 16, reorder="auto", update="auto",
-                 device=0, threads=0, block=0, blocks_per_cu=0, group=0, ranges=0, hubs="auto", lds_kib=0):
+                 device=0, threads=0, block=0, blocks_per_cu=0, group=0, ranges=0, hubs="auto", lds_kib=0,
+                 eager_max=0):
         o = default_options()
         o.sigma, o.slots, o.window = sigma, slots, window
         o.reorder, o.update = REORDER[reorder], UPDATE[update]
         o.device, o.threads, o.block, o.blocks_per_cu = device, threads, block, blocks_per_cu
         o.group, o.ranges, o.hubs = group, ranges, HUBS[hubs]
         o.lds_kib = LDS_OFF if lds_kib is None else lds_kib
+        o.eager_max = eager_max
         rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint32)
         col = np.ascontiguousarray(csr.col if len(csr.col) else np.zeros(1, np.uint32), dtype=np.uint32)
         h = ctypes.c_void_p()
@@ -291,9 +297,11 @@ class Graph:
             src = nxt[:64]
         return lower, upper, used
 
-    def configure(self, update="auto", block=0, blocks_per_cu=0, group=0):
-        """Changes launch settings (update scheme, workgroup shape, group depth)."""
-        _check("blest_configure", lib().blest_configure(self.handle, UPDATE[update], block, blocks_per_cu, group))
+    def configure(self, update="auto", block=0, blocks_per_cu=0, group=0, eager_max=0):
+        """Changes launch settings (update scheme, workgroup shape, group depth,
+        adaptive threshold) without rebuilding."""
+        _check("blest_configure", lib().blest_configure(self.handle, UPDATE[update], block, blocks_per_cu, group,
+                                                        eager_max))
 
     # -- host-side information -------------------------------------------------
     def stats(self) -> dict:
@@ -354,6 +362,13 @@ def level_stats(levels, stream=None) -> dict:
         ctypes.c_void_p(far.data_ptr()), ctypes.c_void_p(close.data_ptr()), _stream_ptr(stream)))
     return {"reached": reached, "total": total, "ecc": ecc, "far": far.to(torch.int64) & 0xFFFFFFFF,
             "closeness": close}
+
+
+def barrier_seconds(device: int = 0, block: int = 1024, rounds: int = 2000) -> float:
+    """Seconds per grid barrier of the persistent launches (blest_barrier_probe)."""
+    x = ctypes.c_double()
+    _check("blest_barrier_probe", lib().blest_barrier_probe(int(device), int(block), int(rounds), ctypes.byref(x)))
+    return float(x.value)
 
 
 def bfs_many(graphs, sources, outs=None, stream=None):

@@ -81,7 +81,7 @@ struct blest_graph {
   std::vector<uint32_t> order_id; // original -> label after the ordering alone (before the hub sort)
   std::vector<uint32_t> orig_id;  // new -> original
   bool identity = true;
-  bool lazy = false;
+  int mode = 0;  // kernel scheme: 0 eager (Algorithm 2), 1 lazy (Algorithm 3), 2 adaptive per level
   int social = 0;
   int hubs_sorted = 0;
   int reorder_used = BLEST_REORDER_NONE;
@@ -168,7 +168,7 @@ bool valid_options(const blest_options& o) {
   if (o.slots != 1 && o.slots != 2 && o.slots != 4 && o.slots != 8) return false;
   if (o.window == 0 || o.window % o.sigma != 0) return false;
   if (o.reorder < BLEST_REORDER_AUTO || o.reorder > BLEST_REORDER_BANDWIDTH) return false;
-  if (o.update < BLEST_UPDATE_AUTO || o.update > BLEST_UPDATE_LAZY) return false;
+  if (o.update < BLEST_UPDATE_AUTO || o.update > BLEST_UPDATE_ADAPTIVE) return false;
   if (o.block % 64 != 0 || o.block > 1024) return false;
   if (o.blocks_per_cu > 16) return false;
   // at most a compute unit's 2048 threads; the grid is further clamped to what the
@@ -191,6 +191,24 @@ hipError_t upload(DevBuf& d, const std::vector<T>& h) {
 
 blest_status set_grid(blest_graph* g);
 hipError_t serial_event(int device);
+
+// Kernel scheme of an update option.  AUTO is the paper's static rule: lazy iff
+// the graph is social-like and its update divergence exceeds 25,000 (Section 4,
+// discussion of Table 3).
+int mode_of(int32_t update, int social, double u_div) {
+  switch (update) {
+    case BLEST_UPDATE_EAGER: return 0;
+    case BLEST_UPDATE_LAZY: return 1;
+    case BLEST_UPDATE_ADAPTIVE: return 2;
+    default: return social && u_div > 25000.0 ? 1 : 0;
+  }
+}
+
+// Adaptive scheme: levels whose queue holds fewer VSSs than this claim eagerly.
+// Default 1/32 of the VSSs: on R-MAT scale 22 the first two and last two levels
+// (1 to 23,741 VSSs) run eagerly, the three dense ones (136K to 1.07M) lazily; on a
+// mesh every level (a few hundred VSSs) runs eagerly.
+uint32_t eager_max_of(const blest_graph* g);
 
 blest_status to_device(blest_graph* g) {
   if (hipSetDevice(g->device) != hipSuccess) return BLEST_ERR_NO_DEVICE;
@@ -247,6 +265,11 @@ uint32_t own_blocks_per_cu(const void* kernel, uint32_t block, uint32_t dyn_lds,
   return nb;
 }
 
+uint32_t eager_max_of(const blest_graph* g) {
+  if (g->opt.eager_max) return g->opt.eager_max;
+  return std::max<uint32_t>(1, g->bvss.num_vss / 32);
+}
+
 // Persistent grid: co-resident workgroups, capped at blocks_per_cu per CU.
 blest_status set_grid(blest_graph* g) {
   const Bvss& b = g->bvss;
@@ -254,8 +277,8 @@ blest_status set_grid(blest_graph* g) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess || cus <= 0)
     return BLEST_ERR_DEVICE;
   g->block = g->opt.block;
-  const bool lds = g->lazy && g->range_words > 0;
-  const void* k = bfs_kernel_symbol(b.sigma, b.slots, g->lazy, g->opt.group, lds);
+  const bool lds = g->mode != 0 && g->range_words > 0;
+  const void* k = bfs_kernel_symbol(b.sigma, b.slots, g->mode, g->opt.group, lds);
   if (lds) {
     // the LDS cache takes what the device leaves beside the kernel's static LDS
     int max_lds = 0;
@@ -299,8 +322,8 @@ SingleWorkspace* single_workspace(blest_graph* g, void* stream, blest_status* st
   hipError_t e = ws->vis.alloc(sizeof(uint32_t) * nw);
   if (e == hipSuccess) e = ws->mark.alloc(32 * nw);
   if (e == hipSuccess) e = ws->front.alloc(sizeof(uint32_t) * 3 * nw);
-  // queues: eager 3 x 32-bit entries, lazy 2 x 64-bit entries (VSS, alpha)
-  if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 4 * std::max<size_t>(g->bvss.num_vss, 1));
+  // queues: eager 3 x 32-bit entries, lazy 2 and adaptive 3 x 64-bit entries (VSS, alpha)
+  if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 6 * std::max<size_t>(g->bvss.num_vss, 1));
   if (e == hipSuccess) e = ws->ctrl.alloc(sizeof(uint32_t) * kCtrlWords);
   if (e == hipSuccess) e = hipMemset(ws->ctrl.p, 0, sizeof(uint32_t) * kCtrlWords);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -373,7 +396,8 @@ BfsParams base_params(const blest_graph* g) {
   p.vss_range = g->d_vss_range.as<uint8_t>();
   p.nranges = g->nranges;
   p.range_len = g->range_len;
-  p.range_words = g->lazy ? g->range_words : 0;
+  p.range_words = g->mode != 0 ? g->range_words : 0;
+  p.eager_max = eager_max_of(g);
   p.lds_cshift = g->lds_cshift;
   p.lds_min_len = std::min<uint32_t>(kLdsMinQueue, std::max<uint32_t>(1, p.range_words / 16));
   return p;
@@ -437,6 +461,7 @@ void blest_default_options(blest_options* o) {
   o->ranges = 0;
   o->hubs = 0;
   o->lds_kib = 0;
+  o->eager_max = 0;
 }
 
 blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, const uint32_t* col_idx,
@@ -498,10 +523,7 @@ blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, cons
     g->compression = g->bvss.num_slices ? (double)g->m / ((double)g->bvss.num_slices * o.sigma) : 0.0;
     // the update-scheme policy reads the divergence of the ordering itself
     g->u_div_paper = update_divergence(g->bvss, 32, 32 / o.sigma);
-    if (o.update == BLEST_UPDATE_AUTO)
-      g->lazy = g->social && g->u_div_paper > 25000.0;
-    else
-      g->lazy = o.update == BLEST_UPDATE_LAZY;
+    g->mode = mode_of(o.update, g->social, g->u_div_paper);
     // Row ranges: with R > 1 every VSS is cut at range boundaries and workgroup b
     // caches range b % R.  The cut multiplies the VSS count (3.6x at R-MAT scale 22
     // with R = 8) and each frontier vertex is then marked by up to R workgroups,
@@ -572,7 +594,7 @@ blest_status blest_bfs(blest_handle h, uint32_t source, int32_t* levels_out, int
     p.src = h->new_id[source];
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = serial_launch(h->device, s, [&] {
-      return launch_bfs(p, h->bvss.sigma, h->bvss.slots, h->lazy, h->opt.group, h->grid, h->block, s);
+      return launch_bfs(p, h->bvss.sigma, h->bvss.slots, h->mode, h->opt.group, h->grid, h->block, s);
     });
     if (e == hipSuccess && parents_out) e = launch_parents(p, h->bvss.sigma, levels_out, parents_out, s);
     return e == hipSuccess ? BLEST_OK : BLEST_ERR_DEVICE;
@@ -586,7 +608,9 @@ blest_status blest_bfs_noalloc(blest_handle h, uint32_t source, int32_t* levels_
   if (source >= h->n) return BLEST_ERR_INVALID_ARGUMENT;
   // the per-call state, carved out of the static scratch in 256-byte-aligned parts
   const uint64_t nw = h->n_words();
-  const uint64_t parts[5] = {4 * nw, 32 * nw, 12 * nw, 16ull * std::max<uint32_t>(h->bvss.num_vss, 1),
+  // queues: eager 3 x 4 bytes, lazy 2 x 8 and adaptive 3 x 8 bytes per VSS
+  const uint64_t qbytes = h->mode == 0 ? 12 : h->mode == 1 ? 16 : 24;
+  const uint64_t parts[5] = {4 * nw, 32 * nw, 12 * nw, qbytes * std::max<uint32_t>(h->bvss.num_vss, 1),
                              4ull * kCtrlWords};
   uint64_t off[5], need = 0;
   for (int i = 0; i < 5; ++i) {
@@ -615,7 +639,7 @@ blest_status blest_bfs_noalloc(blest_handle h, uint32_t source, int32_t* levels_
     hipError_t e = serial_launch(h->device, s, [&] {
       hipError_t z = launch_zero_words(p.ctrl, kCtrlWords, s);
       if (z != hipSuccess) return z;
-      return launch_bfs(p, h->bvss.sigma, h->bvss.slots, h->lazy, h->opt.group, h->grid, h->block, s);
+      return launch_bfs(p, h->bvss.sigma, h->bvss.slots, h->mode, h->opt.group, h->grid, h->block, s);
     });
     return e == hipSuccess ? BLEST_OK : BLEST_ERR_DEVICE;
   } catch (...) {
@@ -780,27 +804,26 @@ blest_status blest_bfs_many(const blest_handle* hs, const uint32_t* sources, uin
   return st;
 }
 
-blest_status blest_configure(blest_handle h, int32_t update, uint32_t block, uint32_t blocks_per_cu, uint32_t group) {
+blest_status blest_configure(blest_handle h, int32_t update, uint32_t block, uint32_t blocks_per_cu, uint32_t group,
+                             uint32_t eager_max) {
   if (!h) return BLEST_ERR_INVALID_ARGUMENT;
   blest_options o = h->opt;
   o.update = update;
   o.block = block ? block : 1024;
   o.blocks_per_cu = blocks_per_cu ? blocks_per_cu : 1;
   o.group = group ? group : 2;
+  o.eager_max = eager_max;
   if (!valid_options(o)) return BLEST_ERR_INVALID_ARGUMENT;
   const blest_options old = h->opt;
-  const bool old_lazy = h->lazy;
+  const int old_mode = h->mode;
   h->opt = o;
-  if (o.update == BLEST_UPDATE_AUTO)
-    h->lazy = h->social && h->u_div_paper > 25000.0;
-  else
-    h->lazy = o.update == BLEST_UPDATE_LAZY;
+  h->mode = mode_of(o.update, h->social, h->u_div_paper);
   if (h->on_device) {
     if (hipSetDevice(h->device) != hipSuccess) return BLEST_ERR_DEVICE;
     blest_status st = set_grid(h);
     if (st != BLEST_OK) {
       h->opt = old;
-      h->lazy = old_lazy;
+      h->mode = old_mode;
       (void)set_grid(h);
       return st;
     }
@@ -825,7 +848,8 @@ blest_status blest_stats(blest_handle h, blest_stats_t* o) {
   o->u_div_native = h->u_div_native;
   o->social_like = h->social;
   o->reorder_used = h->reorder_used;
-  o->update_used = h->lazy ? BLEST_UPDATE_LAZY : BLEST_UPDATE_EAGER;
+  o->update_used = h->mode == 2 ? BLEST_UPDATE_ADAPTIVE : h->mode == 1 ? BLEST_UPDATE_LAZY : BLEST_UPDATE_EAGER;
+  o->eager_max = eager_max_of(h);
   o->nranges = h->nranges;
   o->range_len = h->range_len;
   o->bvss_device_bytes = b.num_slices * (4 + b.sigma / 8) + 4ull * (2ull * b.num_vss + 1) + b.num_vss +
@@ -839,8 +863,8 @@ blest_status blest_stats(blest_handle h, blest_stats_t* o) {
   o->kernel_vgprs = (uint32_t)std::max(h->num_regs, 0);
   o->blocks_per_cu_runtime = h->occ_api;
   o->blocks_per_cu_own = h->occ_own;
-  o->lds_bytes = h->lazy ? 4 * h->range_words : 0;
-  o->lds_chunk_words = h->lazy && h->range_words ? 1u << h->lds_cshift : 0;
+  o->lds_bytes = h->mode != 0 ? 4 * h->range_words : 0;
+  o->lds_chunk_words = h->mode != 0 && h->range_words ? 1u << h->lds_cshift : 0;
   o->hub_cpos = h->hub_cpos;
   return BLEST_OK;
 }
@@ -854,7 +878,7 @@ blest_status blest_footprint(blest_handle h, uint32_t k, uint64_t* bytes) {
     return BLEST_OK;
   }
   const uint64_t nw = h->n_words();
-  const uint64_t q = 4ull * std::max<uint32_t>(h->bvss.num_vss, 1) * 4;
+  const uint64_t q = 4ull * std::max<uint32_t>(h->bvss.num_vss, 1) * 6;
   uint64_t ws;
   if (k == 1)
     ws = 4 * nw * 4 + 32 * nw + q + kCtrlWords * 4;
@@ -954,8 +978,23 @@ blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k
   }
   const uint64_t iters = (uint64_t)maxl + 1;
   if (k == 1) {
-    if (h->lazy) total += iters * 2ull * ((n + 7) / 8);  // Stage 2 reads both visited bitmaps
-    total += 4ull * n + 4ull * reached;                     // level initialisation + level writes
+    // Stage 2 reads both visited bitmaps at every lazy iteration; the adaptive
+    // scheme runs iteration i lazily iff its queue (the VSSs of the sets holding a
+    // vertex of level i - 1) has at least eager_max entries
+    std::vector<uint64_t> queued(iters + 1, 0);
+    for (uint32_t s = 0; s < b.num_sets; ++s) {
+      uint64_t m = 0;
+      for (uint32_t v = s * b.sigma, v1 = std::min<uint32_t>(n, v + b.sigma); v < v1; ++v) m |= lvmask[v];
+      const uint64_t nv = b.real_ptrs[s + 1] - b.real_ptrs[s];
+      for (uint32_t l = 0; m && l < 64 && l < iters; ++l)
+        if ((m >> l) & 1ull) queued[l + 1] += nv;
+    }
+    for (uint64_t i = 1; i <= iters; ++i) {
+      // levels past 63 are not tracked per set; those iterations are counted as eager
+      const bool lazy_iter = h->mode == 1 || (h->mode == 2 && queued[i] >= eager_max_of(h));
+      if (lazy_iter) total += 2ull * ((n + 7) / 8);
+    }
+    total += 4ull * n + 4ull * reached;  // level initialisation + level writes
   } else {
     // Stage 2 per iteration i: a dense iteration (queue >= 1/16 of the VSSs) sweeps
     // every vertex (visited pair, frontier word, state byte: 25 B); a sparse one
@@ -1174,6 +1213,40 @@ blest_status blest_server_destroy(blest_server_handle sv, uint32_t timeout_ms) {
   }
   (void)hipSetDevice(sv->device);
   delete sv;
+  return BLEST_OK;
+}
+
+blest_status blest_barrier_probe(int32_t device, uint32_t block, uint32_t rounds, double* seconds_per_barrier) {
+  if (!seconds_per_barrier || rounds == 0 || block == 0 || block % 64 != 0 || block > 1024)
+    return BLEST_ERR_INVALID_ARGUMENT;
+  int count = 0;
+  if (device < 0 || hipGetDeviceCount(&count) != hipSuccess || device >= count) return BLEST_ERR_NO_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return BLEST_ERR_DEVICE;
+  int cus = 0, nb = 0, regs = 0;
+  const void* k = barrier_probe_symbol();
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)block, 0) != hipSuccess || nb <= 0)
+    return BLEST_ERR_DEVICE;
+  // one workgroup per CU, as the BFS launches of that workgroup size
+  const uint32_t grid = std::min<uint32_t>({(uint32_t)nb, own_blocks_per_cu(k, block, 0, &regs), 1u}) * (uint32_t)cus;
+  DevBuf ctrl;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = ctrl.alloc(4ull * kCtrlWords);
+  if (e == hipSuccess) e = hipMemset(ctrl.p, 0, 4ull * kCtrlWords);
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  float ms[2] = {0, 0};
+  for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first run warms up
+    if (e == hipSuccess) e = hipEventRecord(a, nullptr);
+    if (e == hipSuccess) e = launch_barrier_probe(ctrl.as<uint32_t>(), rounds, grid, block, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(b, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms[rep], a, b);
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (e != hipSuccess) return BLEST_ERR_DEVICE;
+  *seconds_per_barrier = ms[1] / 1000.0 / rounds;
   return BLEST_OK;
 }
 

@@ -64,6 +64,25 @@ __device__ __forceinline__ LazyEntry lazy_entry(const BfsParams& p) {
   return LazyEntry{p.nranges > 1 ? p.vss_range : nullptr};
 }
 
+// Queue entry pushed by an eager level of the adaptive scheme: the 64-bit lazy
+// layout with alpha = 0, because the set's chunk is only final when the level
+// ends; the next level reads it from the claim bitmap instead.
+struct EagerWideEntry {
+  const uint8_t* vss_range;
+  __device__ uint2 operator()(uint32_t v, uint32_t) const {
+    return make_uint2(vss_range ? (v << kRangeBits) | vss_range[v] : v << kRangeBits, 0u);
+  }
+};
+
+template <class QE>
+__device__ __forceinline__ auto eager_entry(const BfsParams& p) {
+  if constexpr (sizeof(QE) == 8) return EagerWideEntry{p.nranges > 1 ? p.vss_range : nullptr};
+  else return RangeEntry{p.nranges > 1 ? p.vss_range : nullptr};
+}
+
+__device__ __forceinline__ uint32_t entry_vss(uint32_t e) { return e >> kRangeBits; }
+__device__ __forceinline__ uint32_t entry_vss(uint2 e) { return e.x >> kRangeBits; }
+
 __device__ __forceinline__ uint32_t to_orig(const BfsParams& p, uint32_t u) {
   return p.orig_id ? p.orig_id[u] : u;
 }
@@ -206,16 +225,21 @@ __device__ __forceinline__ void stage1(const BfsParams& p, uint32_t len, Entry&&
 // to back; a mark is a plain one-byte store of 1 into the row's reached byte.  The
 // stores are idempotent and all write the same value, so no read-modify-write is
 // needed (device-scope atomic ORs cost an order of magnitude more on MI355X).
+// fca: when the queue was pushed by an eager level (adaptive scheme), the claim
+// bitmap of that level, from which alpha is read; nullptr = alpha in the entry.
 template <typename MT, int SLOTS, int G>
-__device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint2* qc, uint32_t len) {
+__device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint2* qc, uint32_t len,
+                                            const uint32_t* fca) {
+  constexpr int SIG = 8 * sizeof(MT);
   using Words = struct { uint32_t w[G][SLOTS]; };
   const __amdgpu_buffer_rsrc_t mrk = mark_buffer(p);
   stage1<MT, SLOTS, G>(
       p, len,
       [&](uint32_t pos, uint32_t& alpha) {
         const uint2 e = qc[pos];
-        alpha = e.y;
-        return e.x >> kRangeBits;
+        const uint32_t v = e.x >> kRangeBits;
+        alpha = fca ? frontier_chunk<SIG>(fca, p.v2r[v]) : e.y;
+        return v;
       },
       [&](const VssGroup<MT, SLOTS, G>& g) {
         Words cw;
@@ -256,9 +280,10 @@ __device__ __forceinline__ void stage1_lazy(const BfsParams& p, const uint2* qc,
 // every group of slices wait for a load when hot and cold rows are interleaved.
 // A mark is a one-byte store into the row's reached byte.
 template <typename MT, int SLOTS, int G>
-__device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint2* qc, uint32_t len, uint32_t* lds) {
+__device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint2* qc, uint32_t len, uint32_t* lds,
+                                                const uint32_t* fca) {
   if (len < p.lds_min_len) {
-    stage1_lazy<MT, SLOTS, G>(p, qc, len);
+    stage1_lazy<MT, SLOTS, G>(p, qc, len, fca);
     return;
   }
   constexpr int SIG = 8 * sizeof(MT);
@@ -300,7 +325,7 @@ __device__ __forceinline__ void stage1_lazy_lds(const BfsParams& p, const uint2*
       const uint32_t v = e.x >> kRangeBits;
       mb = p.vss_beg[v];
       me = p.vss_beg[v + 1];
-      ma = e.y;
+      ma = fca ? frontier_chunk<SIG>(fca, p.v2r[v]) : e.y;
     }
     // G picked lanes at a time (uniform); missing ones read an empty VSS.  The
     // next group's slice loads are issued before the current group is applied.
@@ -475,9 +500,12 @@ constexpr uint32_t kPushList = 64;
 // reserves queue space once at the end: on high-diameter graphs, where a level has
 // a few thousand claims, a reservation per wavefront put thousands of returning
 // atomics on one counter, serialised, into every level.
-template <typename MT, int SLOTS, int G>
-__device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t* qc, uint32_t len,
-                                             const uint32_t* fc, uint32_t* fn, uint32_t* qn, uint32_t* qlen,
+// QE is the queue entry: uint32_t (eager scheme: VSS and range) or uint2 (adaptive
+// scheme: the lazy layout).  fc = the claim bitmap of the previous level, from
+// which alpha is read; nullptr (uint2 entries only) = alpha in the entry.
+template <typename MT, int SLOTS, int G, class QE>
+__device__ __forceinline__ void stage1_eager(const BfsParams& p, const QE* qc, uint32_t len,
+                                             const uint32_t* fc, uint32_t* fn, QE* qn, uint32_t* qlen,
                                              int32_t level) {
   constexpr int SIG = 8 * sizeof(MT);
   struct Pre {
@@ -501,7 +529,7 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
     }
     uint32_t total;
     const uint32_t pos = wave_reserve(qlen, n[0], total);
-    wave_push<1>(qn, pos, n[0], b, n, b /* tags: unused */, range_entry(p));
+    wave_push<1>(qn, pos, n[0], b, n, b /* tags: unused */, eager_entry<QE>(p));
     if (lane == 0) s_cnt[wave] = 0;
   };
   // queues every wavefront's list with one reservation for the workgroup
@@ -526,7 +554,7 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
       s_qbase = run ? atomicAdd(qlen, run) : 0u;
     }
     __syncthreads();
-    wave_push<1>(qn, s_qbase + s_tot[wave] + incl - n[0], n[0], b, n, b /* tags: unused */, range_entry(p));
+    wave_push<1>(qn, s_qbase + s_tot[wave] + incl - n[0], n[0], b, n, b /* tags: unused */, eager_entry<QE>(p));
   };
   // Besides the visited words, a hit's original ID and its set's VSS range are
   // loaded up front, in parallel, so that neither the level store nor the push
@@ -548,8 +576,10 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
     return pre;
   };
   auto entry = [&](uint32_t pos, uint32_t& alpha) {
-    const uint32_t v = qc[pos] >> kRangeBits;
-    alpha = frontier_chunk<SIG>(fc, p.v2r[v]);
+    const QE e = qc[pos];
+    const uint32_t v = entry_vss(e);
+    if constexpr (sizeof(QE) == 8) alpha = fc ? frontier_chunk<SIG>(fc, p.v2r[v]) : e.y;
+    else alpha = frontier_chunk<SIG>(fc, p.v2r[v]);
     return v;
   };
   stage1<MT, SLOTS, G>(p, len, entry, issue, [&](const VssGroup<MT, SLOTS, G>& g, const Pre& pre) {
@@ -595,7 +625,7 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
     if (rtot > kPushList) {
       uint32_t total;
       const uint32_t pos = wave_reserve(qlen, cnt, total);
-      wave_push<G * SLOTS>(qn, pos, cnt, vb, vn, vb /* tags: unused */, range_entry(p));
+      wave_push<G * SLOTS>(qn, pos, cnt, vb, vn, vb /* tags: unused */, eager_entry<QE>(p));
       return;
     }
     uint32_t at = used + rincl - nr;
@@ -612,25 +642,37 @@ __device__ __forceinline__ void stage1_eager(const BfsParams& p, const uint32_t*
 }
 
 // Clears the frontier chunks of the sets named by queue qold (eager scheme).
-template <int SIG>
-__device__ __forceinline__ void clear_chunks(const BfsParams& p, uint32_t* f, const uint32_t* qold, uint32_t len) {
+template <int SIG, class QE>
+__device__ __forceinline__ void clear_chunks(const BfsParams& p, uint32_t* f, const QE* qold, uint32_t len) {
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nt = gridDim.x * blockDim.x;
   // the highest-numbered threads take the clears: on the small levels of
   // high-diameter graphs they have no Stage 1 work, so the clears' dependent loads
   // stay off the Stage 1 chain of the low-numbered wavefronts
   for (uint32_t i = nt - 1 - tid; i < len; i += nt) {
-    const uint32_t ss = p.v2r[qold[i] >> kRangeBits];
+    const uint32_t ss = p.v2r[entry_vss(qold[i])];
     if (SIG == 8) reinterpret_cast<uint8_t*>(f)[ss] = 0;
     else if (SIG == 16) reinterpret_cast<uint16_t*>(f)[ss] = 0;
     else f[ss] = 0;
   }
 }
 
-template <typename MT, int SLOTS, bool LAZY, int G, bool LDSVIS>
+// MODE: kEager (Algorithm 2 every level), kLazy (Algorithm 3 every level) or
+// kAdaptive: each level picks, on the device, from the length of its queue (the
+// same value in every workgroup): levels with fewer than p.eager_max queued VSSs
+// claim eagerly with one grid barrier and no vertex sweep; larger ones mark lazily
+// and sweep (two barriers).  State shared across the switch: the visited bitmap
+// (both schemes keep it exact), the reached bytes (zero for unvisited vertices;
+// the lazy sweep masks visited ones), three claim bitmaps (an eager level's claims
+// give the next level its alpha; they are cleared sparsely two levels later) and
+// three queues of 64-bit lazy-layout entries.
+constexpr int kEager = 0, kLazy = 1, kAdaptive = 2;
+
+template <typename MT, int SLOTS, int MODE, int G, bool LDSVIS>
 __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
   extern __shared__ uint32_t lds_vis[];
   constexpr int SIG = 8 * sizeof(MT);
+  constexpr bool MARKS = MODE != kEager;  // reached bytes in use
   uint32_t* ctrl = p.ctrl;
   uint32_t* qlen = ctrl + kQlen;  // qlen[i] at qlen[i * kLine]
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -642,10 +684,10 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
 
   // ---- initialisation (Algorithm 2/3, first lines) ----
   for (uint32_t i = tid; i < p.n; i += nt) p.levels[i] = (i == so) ? 0 : -1;
-  if (LAZY) {
-    for (uint32_t t = tid; t < p.n_words; t += nt) {
-      const uint32_t b = (t == sw) ? sbit : 0u;
-      p.vis[t] = b;
+  for (uint32_t t = tid; t < p.n_words; t += nt) {
+    const uint32_t b = (t == sw) ? sbit : 0u;
+    p.vis[t] = b;
+    if (MARKS) {
       // the word's 32 reached bytes: zero, except the source's
       uint32_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (t == sw) z[(p.src & 31) >> 2] = 1u << (8 * (p.src & 3));
@@ -653,20 +695,19 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
       mb[0] = make_uint4(z[0], z[1], z[2], z[3]);
       mb[1] = make_uint4(z[4], z[5], z[6], z[7]);
     }
-  } else {
-    for (uint32_t t = tid; t < p.n_words; t += nt) {
-      const uint32_t b = (t == sw) ? sbit : 0u;
-      p.vis[t] = b;
-      p.front[t] = b;
+    if (MODE != kLazy) {
+      // eager: the source is the level-0 claim; adaptive: alpha of level 1 is in
+      // the entries, and every claim bitmap starts empty
+      p.front[t] = MODE == kEager ? b : 0u;
       p.front[p.n_words + t] = 0;
       p.front[2 * p.n_words + t] = 0;
     }
   }
-  if (LAZY) {
+  if (MODE == kEager) {
+    for (uint32_t j = tid; j < q0n; j += nt) p.queue[j] = range_entry(p)(q0b + j, 0u);
+  } else {
     const uint32_t a0 = 1u << (p.src % SIG);  // the source's bit in its set's frontier chunk
     for (uint32_t j = tid; j < q0n; j += nt) reinterpret_cast<uint2*>(p.queue)[j] = lazy_entry(p)(q0b + j, a0);
-  } else {
-    for (uint32_t j = tid; j < q0n; j += nt) p.queue[j] = range_entry(p)(q0b + j, 0u);
   }
   if (tid == 0) {
     qlen[0] = q0n;
@@ -676,22 +717,23 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
   }
   grid_barrier(ctrl);
 
+  bool prev_eager = false, prev2_eager = false;  // modes of levels l - 1 and l - 2 (adaptive)
   for (int32_t level = 1; level <= (int32_t)p.n + 1; ++level) {
-    if (LAZY) {
+    if (MODE == kLazy) {
       const uint2* qc = reinterpret_cast<const uint2*>(p.queue) + ((level - 1) & 1) * p.qcap;
       uint2* qn = reinterpret_cast<uint2*>(p.queue) + (level & 1) * p.qcap;
       const uint32_t len = ld_relaxed(qlen + ((level - 1) % 3) * kLine);
       uint32_t* qnext_len = qlen + (level % 3) * kLine;
       if (tid == 0) __hip_atomic_store(qlen + ((level + 1) % 3) * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (LDSVIS)
-        stage1_lazy_lds<MT, SLOTS, G>(p, qc, len, lds_vis);
+        stage1_lazy_lds<MT, SLOTS, G>(p, qc, len, lds_vis, nullptr);
       else
-        stage1_lazy<MT, SLOTS, G>(p, qc, len);
+        stage1_lazy<MT, SLOTS, G>(p, qc, len, nullptr);
       grid_barrier(ctrl);
       stage2_lazy<SIG>(p, qn, qnext_len, level);
       grid_barrier(ctrl);
       if (ld_relaxed(qnext_len) == 0) break;
-    } else {
+    } else if (MODE == kEager) {
       const uint32_t* qc = p.queue + ((level - 1) % 3) * p.qcap;
       uint32_t* qn = p.queue + (level % 3) * p.qcap;
       const uint32_t* qold = p.queue + ((level + 1) % 3) * p.qcap;  // queue of level - 2
@@ -706,6 +748,36 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
       stage1_eager<MT, SLOTS, G>(p, qc, len, fc, fn, qn, qnext_len, level);
       grid_barrier(ctrl);
       if (ld_relaxed(qnext_len) == 0) break;
+    } else {
+      uint2* q2 = reinterpret_cast<uint2*>(p.queue);
+      const uint2* qc = q2 + ((level - 1) % 3) * p.qcap;
+      uint2* qn = q2 + (level % 3) * p.qcap;
+      const uint32_t len = ld_relaxed(qlen + ((level - 1) % 4) * kLine);
+      uint32_t* qnext_len = qlen + (level % 4) * kLine;
+      if (tid == 0) __hip_atomic_store(qlen + ((level + 1) % 4) * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t* fc = prev_eager ? p.front + ((level - 1) % 3) * p.n_words : nullptr;
+      if (prev2_eager) {
+        // the claims of level - 2 (sets of the queue it pushed) leave their bitmap
+        const uint2* qold = q2 + ((level + 1) % 3) * p.qcap;
+        clear_chunks<SIG>(p, p.front + ((level + 1) % 3) * p.n_words, qold,
+                          ld_relaxed(qlen + ((level + 2) % 4) * kLine));
+      }
+      const bool eager = len < p.eager_max;
+      if (eager) {
+        stage1_eager<MT, SLOTS, G>(p, qc, len, fc, p.front + (level % 3) * p.n_words, qn, qnext_len, level);
+        grid_barrier(ctrl);
+      } else {
+        if (LDSVIS)
+          stage1_lazy_lds<MT, SLOTS, G>(p, qc, len, lds_vis, fc);
+        else
+          stage1_lazy<MT, SLOTS, G>(p, qc, len, fc);
+        grid_barrier(ctrl);
+        stage2_lazy<SIG>(p, qn, qnext_len, level);
+        grid_barrier(ctrl);
+      }
+      if (ld_relaxed(qnext_len) == 0) break;
+      prev2_eager = prev_eager;
+      prev_eager = eager;
     }
   }
 }
@@ -741,30 +813,42 @@ __global__ void parents_scan(BfsParams p, const int32_t* __restrict__ levels, in
   }
 }
 
-template <typename MT, int SLOTS, bool LAZY, bool LDSVIS>
+template <typename MT, int SLOTS, int MODE, bool LDSVIS>
 const void* sym_group(uint32_t group) {
   switch (group) {
-    case 1: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 1, LDSVIS>);
-    case 2: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 2, LDSVIS>);
-    case 4: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, LAZY, 4, LDSVIS>);
+    case 1: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, MODE, 1, LDSVIS>);
+    case 2: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, MODE, 2, LDSVIS>);
+    case 4: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, MODE, 4, LDSVIS>);
+    default: return nullptr;
+  }
+}
+
+template <typename MT, int SLOTS>
+const void* sym_mode(int mode, uint32_t group, bool lds) {
+  // the LDS-visited variants exist for the schemes that mark lazily
+  switch (mode) {
+    case kEager: return sym_group<MT, SLOTS, kEager, false>(group);
+    case kLazy: return lds ? sym_group<MT, SLOTS, kLazy, true>(group) : sym_group<MT, SLOTS, kLazy, false>(group);
+    case kAdaptive:
+      return lds ? sym_group<MT, SLOTS, kAdaptive, true>(group) : sym_group<MT, SLOTS, kAdaptive, false>(group);
     default: return nullptr;
   }
 }
 
 template <typename MT>
-const void* sym_slots(uint32_t slots, bool lazy, uint32_t group, bool lds) {
-  // the LDS-visited variant exists for the lazy scheme only
+const void* sym_slots(uint32_t slots, int mode, uint32_t group, bool lds) {
   switch (slots) {
-    case 1: return lazy ? (lds ? sym_group<MT, 1, true, true>(group) : sym_group<MT, 1, true, false>(group))
-                        : sym_group<MT, 1, false, false>(group);
-    case 2: return lazy ? (lds ? sym_group<MT, 2, true, true>(group) : sym_group<MT, 2, true, false>(group))
-                        : sym_group<MT, 2, false, false>(group);
-    case 4: return lazy ? (lds ? sym_group<MT, 4, true, true>(group) : sym_group<MT, 4, true, false>(group))
-                        : sym_group<MT, 4, false, false>(group);
-    case 8: return lazy ? (lds ? sym_group<MT, 8, true, true>(group) : sym_group<MT, 8, true, false>(group))
-                        : sym_group<MT, 8, false, false>(group);
+    case 1: return sym_mode<MT, 1>(mode, group, lds);
+    case 2: return sym_mode<MT, 2>(mode, group, lds);
+    case 4: return sym_mode<MT, 4>(mode, group, lds);
+    case 8: return sym_mode<MT, 8>(mode, group, lds);
     default: return nullptr;
   }
+}
+
+// `rounds` grid barriers and nothing else, in the persistent kernels' launch shape.
+__global__ __launch_bounds__(1024) void barrier_probe(uint32_t* ctrl, uint32_t rounds) {
+  for (uint32_t r = 0; r < rounds; ++r) grid_barrier(ctrl);
 }
 
 __global__ void zero_words(uint32_t* __restrict__ p, uint32_t n) {
@@ -796,24 +880,32 @@ hipError_t noalloc_scratch(int device, void** ptr) {
   return hipSuccess;
 }
 
+hipError_t launch_barrier_probe(uint32_t* ctrl, uint32_t rounds, uint32_t grid, uint32_t block, hipStream_t stream) {
+  void* args[] = {&ctrl, &rounds};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&barrier_probe), dim3(grid), dim3(block), args, 0,
+                                    stream);
+}
+
+const void* barrier_probe_symbol() { return reinterpret_cast<const void*>(&barrier_probe); }
+
 hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t stream) {
   hipLaunchKernelGGL(zero_words, dim3(1), dim3(512), 0, stream, p, n);
   return hipGetLastError();
 }
 
-const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, bool lds) {
+const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, int mode, uint32_t group, bool lds) {
   switch (sigma) {
-    case 8: return sym_slots<uint8_t>(slots, lazy, group, lds);
-    case 16: return sym_slots<uint16_t>(slots, lazy, group, lds);
-    case 32: return sym_slots<uint32_t>(slots, lazy, group, lds);
+    case 8: return sym_slots<uint8_t>(slots, mode, group, lds);
+    case 16: return sym_slots<uint16_t>(slots, mode, group, lds);
+    case 32: return sym_slots<uint32_t>(slots, mode, group, lds);
     default: return nullptr;
   }
 }
 
-hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, uint32_t grid,
+hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, int mode, uint32_t group, uint32_t grid,
                       uint32_t block, hipStream_t stream) {
-  const bool lds = lazy && p.range_words > 0;
-  const void* k = bfs_kernel_symbol(sigma, slots, lazy, group, lds);
+  const bool lds = mode != kEager && p.range_words > 0;
+  const void* k = bfs_kernel_symbol(sigma, slots, mode, group, lds);
   if (!k || grid % p.nranges != 0) return hipErrorInvalidValue;
   BfsParams copy = p;
   void* args[] = {&copy};

@@ -28,8 +28,8 @@ struct BfsParams {
   // per-call workspace
   uint32_t* vis;            // visited bits, n_words
   uint8_t* mark;            // lazy: reached byte per vertex, 32 * n_words
-  uint32_t* front;          // eager: 3 * n_words (the lazy scheme keeps alpha in its queue entries)
-  uint32_t* queue;          // eager: 3 * qcap 32-bit entries; lazy: 2 * qcap 64-bit entries (VSS, alpha)
+  uint32_t* front;          // eager, adaptive: 3 * n_words (the lazy scheme keeps alpha in its queue entries)
+  uint32_t* queue;          // eager: 3 * qcap 32-bit entries; lazy: 2, adaptive: 3 * qcap 64-bit entries (VSS, alpha)
   uint32_t* ctrl;           // kCtrlWords
   int32_t* levels;          // n, original IDs
   uint32_t n, n_words, num_sets, num_vss, qcap;
@@ -39,6 +39,7 @@ struct BfsParams {
   uint32_t range_words;     // visited words of a range cached in LDS (0: none)
   uint32_t lds_cshift;      // the cache holds words 0 .. 2^lds_cshift - 1 of every 64-word chunk
   uint32_t lds_min_len;     // lazy: levels with fewer queue entries skip the LDS cache
+  uint32_t eager_max;       // adaptive: levels with fewer queued VSSs claim eagerly
 };
 
 // Queue entries carry the VSS's row range in their low bits.
@@ -46,18 +47,19 @@ constexpr uint32_t kRangeBits = 5;
 constexpr uint32_t kMaxRanges = 1u << kRangeBits;
 constexpr uint32_t kMaxLdsBytes = 128 * 1024;
 
-// Persistent single-source BFS; lazy selects Algorithm 3, otherwise Algorithm 2.
+// Persistent single-source BFS.  mode: 0 = Algorithm 2 (eager) every level,
+// 1 = Algorithm 3 (lazy) every level, 2 = per level by queue length (adaptive).
 // grid must be co-resident (the call uses a cooperative launch) and a multiple of
 // p.nranges.  group = VSSs whose slice loads a wavefront keeps in flight together
 // (1, 2, 4).  With p.range_words > 0 the lazy kernel caches, per workgroup, the
 // visited words 0 .. 2^lds_cshift - 1 of every 64-word chunk of the workgroup's
 // row range in LDS (4 * range_words bytes of dynamic LDS); other rows are checked
 // in memory.
-hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, uint32_t grid,
+hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, int mode, uint32_t group, uint32_t grid,
                       uint32_t block, hipStream_t stream);
 
 // Returns the kernel symbol used by launch_bfs (for occupancy queries).
-const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, bool lazy, uint32_t group, bool lds);
+const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, int mode, uint32_t group, bool lds);
 
 // k-source BFS (k <= 64): per-vertex 64-bit frontier and visited words, bit j for
 // source j.
@@ -201,6 +203,10 @@ hipError_t launch_parents(const BfsParams& p, uint32_t sigma, const int32_t* lev
 // Device address of the allocation-free entry point's static scratch array on
 // `device` (which must be the current device); looked up once per device.
 hipError_t noalloc_scratch(int device, void** ptr);
+
+// A persistent launch doing `rounds` grid barriers (ctrl: kCtrlWords, zeroed).
+hipError_t launch_barrier_probe(uint32_t* ctrl, uint32_t rounds, uint32_t grid, uint32_t block, hipStream_t stream);
+const void* barrier_probe_symbol();
 
 // Zeroes n 32-bit words at p with one small ordinary launch on `stream`.
 hipError_t launch_zero_words(uint32_t* p, uint32_t n, hipStream_t stream);

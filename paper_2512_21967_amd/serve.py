@@ -126,12 +126,15 @@ class Server:
                 nbytes = self.footprint(r.graph, r.k)
                 if self.outstanding + nbytes > self.budget:
                     break
-                out = self.alloc(r.k, self.graphs[r.graph].n)
-                t = self.dev.submit(self.index[r.graph], r.sources, out)
+                # the output is referenced by the request only, so that releasing the
+                # request frees it
+                r.levels = self.alloc(r.k, self.graphs[r.graph].n)
+                t = self.dev.submit(self.index[r.graph], r.sources, r.levels)
                 if t is None:  # the device's ring is full: wait for releases
+                    r.levels = None
                     break
                 waiting.popleft()
-                r.ticket, r.levels, r.submitted_at = t, out, time.perf_counter()
+                r.ticket, r.submitted_at = t, time.perf_counter()
                 self.outstanding += nbytes
                 self.peak_bytes = max(self.peak_bytes, self.outstanding)
                 inflight[t] = r

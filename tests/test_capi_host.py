@@ -375,6 +375,42 @@ def test_footprint_and_model_bytes():
     assert 4 * gr.n < b_one < b_all
 
 
+@pytest.mark.parametrize("update", ["eager", "lazy", "adaptive"])
+def test_model_bytes_single_source_formula(update):
+    """k = 1 algorithmic bytes: for every iteration i = 1 .. max level + 1 and every
+    slice set holding a vertex of level i - 1, its unpadded slices at 4 + sigma/8
+    bytes, its sigma/8-byte frontier chunk and 8 bytes per VSS; 2 n/8 bytes of
+    visited bitmaps per lazily run iteration (adaptive: queue >= eager_max); 4n bytes
+    of level initialisation and 4 bytes per reached vertex.  Restated here from the
+    exported arrays and the oracle's levels."""
+    import oracle
+    gr = inputs.rmat_workload(11, 8, seed=3, permute_seed=4)
+    g = host_graph(gr, reorder="compression", window=256, update=update, eager_max=7)
+    st = g.stats()
+    sig = st["sigma"]
+    new_id = g.export("new_id")
+    rp = g.export("real_ptrs").astype(np.int64)
+    vb = g.export("vss_begin").astype(np.int64)
+    for s in (0, 5, 77):
+        lv = oracle.bfs(gr, int(inputs.sources(gr, seed=s, k=1)[0]))
+        lv_new = np.full(gr.n, -1, np.int64)
+        lv_new[new_id] = lv
+        sets = np.arange(gr.n) // sig
+        total = 0
+        maxl = int(lv.max())
+        for i in range(1, maxl + 2):
+            active = np.unique(sets[lv_new == i - 1])
+            active = active[rp[active + 1] > rp[active]]
+            slices = vb[rp[active + 1]] - vb[rp[active]]
+            nvss = rp[active + 1] - rp[active]
+            total += int(np.sum(slices * (4 + sig // 8) + sig // 8 + 8 * nvss))
+            queued = int(nvss.sum())
+            if update == "lazy" or (update == "adaptive" and queued >= 7):
+                total += 2 * ((gr.n + 7) // 8)
+        total += 4 * gr.n + 4 * int(np.sum(lv >= 0))
+        assert g.model_bytes(lv) == total, (update, s)
+
+
 def test_traffic_record_hash_scope():
     """The traffic record's hash covers the files that build the single-source
     kernel; every one of them exists, and the hash changes with their content."""

@@ -40,6 +40,7 @@ def s22():
 
 
 def test_s22_all_64_sources(s22):
+    """Every source under the static rule (lazy here) and under the adaptive scheme."""
     gr, g = s22
     st = g.stats()
     assert st["update_used"] == "lazy" and st["hubs_sorted"] == 1
@@ -47,10 +48,13 @@ def test_s22_all_64_sources(s22):
     say(f"S22: n={gr.n} arcs={gr.nnz} VSS={st['num_vss']} grid={st['grid']}x{st['block']}")
     want = oracle_pool.rows(gr, srcs)
     out = torch.empty(gr.n, dtype=torch.int32, device="cuda")
-    for j, s in enumerate(srcs):
-        g.bfs(int(s), levels=out)
-        got = out.cpu().numpy()
-        np.testing.assert_array_equal(got, want[j], err_msg=f"S22 source {int(s)} (#{j})")
+    for update in ("auto", "adaptive"):
+        g.configure(update=update)
+        for j, s in enumerate(srcs):
+            g.bfs(int(s), levels=out)
+            got = out.cpu().numpy()
+            np.testing.assert_array_equal(got, want[j], err_msg=f"S22 {update} source {int(s)} (#{j})")
+    g.configure(update="auto")
 
 
 def test_s20_k64_all_rows():
@@ -73,9 +77,11 @@ def test_grid4096_all_16_sources():
     say(f"grid 4096^2: n={gr.n} arcs={gr.nnz} update={st['update_used']}")
     want = oracle_pool.rows(gr, srcs)
     out = torch.empty(gr.n, dtype=torch.int32, device="cuda")
-    for j, s in enumerate(srcs):
-        g.bfs(int(s), levels=out)
-        np.testing.assert_array_equal(out.cpu().numpy(), want[j], err_msg=f"grid source {int(s)} (#{j})")
+    for update in ("auto", "adaptive"):
+        g.configure(update=update)
+        for j, s in enumerate(srcs):
+            g.bfs(int(s), levels=out)
+            np.testing.assert_array_equal(out.cpu().numpy(), want[j], err_msg=f"grid {update} source {int(s)} (#{j})")
     assert want.max() > 4000  # thousands of levels
 
 

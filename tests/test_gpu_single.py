@@ -40,7 +40,7 @@ def check_sources(gr, g, srcs, with_parents=False):
             np.testing.assert_array_equal(got, want, err_msg=f"{gr.name or 'graph'} source {s}")
 
 
-@pytest.mark.parametrize("update", ["eager", "lazy"])
+@pytest.mark.parametrize("update", ["eager", "lazy", "adaptive"])
 @pytest.mark.parametrize("name", sorted(families.ALL_FAMILIES))
 def test_closed_form_families_every_source(name, update):
     gr, lv = families.ALL_FAMILIES[name]()
@@ -49,7 +49,7 @@ def test_closed_form_families_every_source(name, update):
         np.testing.assert_array_equal(run(g, s), lv(s), err_msg=f"{name} source {s} ({update})")
 
 
-@pytest.mark.parametrize("update", ["eager", "lazy"])
+@pytest.mark.parametrize("update", ["eager", "lazy", "adaptive"])
 @pytest.mark.parametrize("sigma,slots", [(8, 1), (8, 2), (8, 4), (8, 8), (16, 4), (32, 2)])
 def test_rmat_widths_and_slots(sigma, slots, update):
     gr = inputs.rmat_workload(13, 16, seed=sigma * 10 + slots, permute_seed=1)
@@ -57,7 +57,7 @@ def test_rmat_widths_and_slots(sigma, slots, update):
     check_sources(gr, g, inputs.sources(gr, seed=3, k=4))
 
 
-@pytest.mark.parametrize("update", ["eager", "lazy"])
+@pytest.mark.parametrize("update", ["eager", "lazy", "adaptive"])
 @pytest.mark.parametrize("reorder", ["compression", "bandwidth"])
 def test_reordered_graphs_map_back(reorder, update):
     if reorder == "compression":
@@ -70,7 +70,7 @@ def test_reordered_graphs_map_back(reorder, update):
     check_sources(gr, g, inputs.sources(gr, seed=8, k=4))
 
 
-@pytest.mark.parametrize("update", ["eager", "lazy"])
+@pytest.mark.parametrize("update", ["eager", "lazy", "adaptive"])
 def test_parents_pass_graph500_checks(update):
     gr = inputs.rmat_workload(12, 16, seed=6, permute_seed=3)
     g = blest.Graph(gr, update=update, reorder="compression", window=512)
@@ -80,7 +80,7 @@ def test_parents_pass_graph500_checks(update):
     check_sources(grid, g, inputs.sources(grid, seed=2, k=2), with_parents=True)
 
 
-@pytest.mark.parametrize("update", ["eager", "lazy"])
+@pytest.mark.parametrize("update", ["eager", "lazy", "adaptive"])
 def test_directed_graphs_follow_out_edges(update):
     rng = np.random.default_rng(11)
     for n in (2, 31, 33, 257, 3000):
@@ -90,7 +90,7 @@ def test_directed_graphs_follow_out_edges(update):
         check_sources(gr, g, range(0, n, max(1, n // 5)))
 
 
-@pytest.mark.parametrize("update", ["eager", "lazy"])
+@pytest.mark.parametrize("update", ["eager", "lazy", "adaptive"])
 def test_degenerate_inputs(update):
     # one vertex, no arcs
     one = inputs.from_arcs(1, [], [], False)
@@ -110,7 +110,7 @@ def test_degenerate_inputs(update):
 
 def test_repeated_runs_identical():
     gr = inputs.rmat_workload(14, 16, seed=9, permute_seed=4)
-    for update in ("eager", "lazy"):
+    for update in ("eager", "lazy", "adaptive"):
         g = blest.Graph(gr, update=update, reorder="none")
         s = int(inputs.sources(gr, seed=1, k=1)[0])
         want = oracle.bfs(gr, s)
@@ -154,13 +154,13 @@ def test_streams_and_async():
 def test_full_size_s16_config():
     """R-MAT scale 16, edge factor 16, plain ordering (the small benchmark config)."""
     gr = inputs.rmat_workload(16, 16, seed=1)
-    for update in ("eager", "lazy"):
+    for update in ("eager", "lazy", "adaptive"):
         g = blest.Graph(gr, reorder="none", update=update)
         check_sources(gr, g, inputs.sources(gr, seed=1, k=3))
 
 
 @pytest.mark.parametrize("ranges", [1, 2, 8, 32])
-@pytest.mark.parametrize("update", ["lazy", "eager"])
+@pytest.mark.parametrize("update", ["lazy", "eager", "adaptive"])
 def test_row_ranges(ranges, update):
     """VSSs cut at row-range boundaries; the lazy kernel keeps each workgroup's
     range of visited bits in LDS."""
@@ -205,3 +205,62 @@ def test_full_size_s22_config_sampled_sources():
     assert st["update_used"] == "lazy" and st["nranges"] == 1 and st["hubs_sorted"] == 1
     assert st["lds_bytes"] == 128 * 1024 and st["lds_bytes"] * 8 < gr.n
     check_sources(gr, g, inputs.sources(gr, seed=3, k=64)[:2])
+
+
+def _csr_arcs(gr, offset):
+    rows = np.repeat(np.arange(gr.n, dtype=np.int64), np.diff(gr.row_ptr.astype(np.int64)))
+    return rows + offset, gr.col.astype(np.int64) + offset
+
+
+@pytest.mark.parametrize("eager_max", [1, 3, 40, 400, 1 << 30])
+@pytest.mark.parametrize("lds_kib", [0, None])
+def test_adaptive_switches_between_schemes(eager_max, lds_kib):
+    """Two R-MAT blobs joined by a 2,000-vertex path: the blobs' middle levels queue
+    many VSSs, the path's levels one or two, so with thresholds between those sizes
+    the BFS switches between eager and lazy levels several times (eager after
+    eager, eager after lazy, lazy after eager, lazy after lazy); 1 and 2^30 make
+    every level lazy or eager."""
+    a = inputs.rmat(13, 8, seed=31)
+    b = inputs.rmat(12, 16, seed=32)
+    plen = 2000
+    base_p, base_b = a.n, a.n + plen
+    sa, da = _csr_arcs(a, 0)
+    sb, db = _csr_arcs(b, base_b)
+    chain = np.concatenate([[0], np.arange(base_p, base_b), [base_b]]).astype(np.int64)
+    n = base_b + b.n
+    gr = inputs.from_arcs(n, np.concatenate([sa, sb, chain[:-1]]), np.concatenate([da, db, chain[1:]]), True)
+    g = blest.Graph(gr, update="adaptive", reorder="none", eager_max=eager_max, lds_kib=lds_kib)
+    st = g.stats()
+    assert st["update_used"] == "adaptive" and st["eager_max"] == eager_max
+    srcs = [0, 17, base_p + 5, base_p + plen // 2, base_b, base_b + 3, n - 1]
+    check_sources(gr, g, srcs)
+    out = torch.empty(gr.n, dtype=torch.int32, device="cuda")
+    for s in srcs[:3]:  # the allocation-free entry point runs the same scheme
+        g.bfs_noalloc(s, out)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), oracle.bfs(gr, s))
+
+
+def test_adaptive_default_threshold_on_rmat_and_grid():
+    gr = inputs.rmat_workload(17, 16, seed=5, permute_seed=6)
+    g = blest.Graph(gr, update="adaptive", reorder="compression", window=4096)
+    assert g.stats()["eager_max"] == max(1, g.stats()["num_vss"] // 32)
+    check_sources(gr, g, inputs.sources(gr, seed=4, k=4), with_parents=True)
+    grid = inputs.grid_workload(128, 0.9, seed=5, permute_seed=6)
+    g = blest.Graph(grid, update="adaptive", reorder="bandwidth")
+    check_sources(grid, g, inputs.sources(grid, seed=4, k=3))
+
+
+def test_occupancy_answer_and_scalar_registers():
+    """The eager kernel at sigma 8, one slot, group depth 1 uses 64 vector registers,
+    which alone would allow 8 wavefronts per SIMD; its scalar registers allow 7.  The
+    grid asked for as two 1024-thread workgroups per CU is held to one (the
+    runtime's answer is printed for the record)."""
+    gr = inputs.rmat_workload(12, 16, seed=2, permute_seed=7)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    g = blest.Graph(gr, update="eager", reorder="none", slots=1, group=1, block=1024, blocks_per_cu=2)
+    st = g.stats()
+    print(f"eager sigma 8 slots 1 group 1: vgprs {st['kernel_vgprs']} runtime {st['blocks_per_cu_runtime']} "
+          f"own {st['blocks_per_cu_own']} grid {st['grid']}", flush=True)
+    assert st["blocks_per_cu_own"] == 1 and st["grid"] == cus
+    check_sources(gr, g, inputs.sources(gr, seed=5, k=2))
