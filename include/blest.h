@@ -94,6 +94,9 @@ typedef struct {
                           chunk of the range, C as large as fits */
   uint32_t eager_max;  /* BLEST_UPDATE_ADAPTIVE: levels with fewer queued VSSs run eagerly
                           (0 = num_vss / 32) */
+  uint32_t pack;       /* 0 = auto: with sigma 8, slots <= 4 and n <= 2^24 the single-source kernel
+                          reads each slice as one 32-bit word (row ID | mask << 24, an extra
+                          4 bytes per slice on the device); 1 = off */
 } blest_options;
 
 #define BLEST_LDS_OFF 0xFFFFFFFFu
@@ -128,6 +131,7 @@ typedef struct {
   uint32_t blocks_per_cu_own;   /* workgroups per CU by the kernel's registers and LDS (gfx950 rules);
                                    the grid uses the smaller of the two and blocks_per_cu */
   uint32_t eager_max;           /* adaptive threshold in effect (queued VSSs) */
+  int32_t packed;               /* 1 if the single-source kernel reads packed slices */
 } blest_stats_t;
 
 /* Fills *opt with the defaults listed above. */

@@ -52,7 +52,7 @@ class Options(ctypes.Structure):
                 ("reorder", ctypes.c_int32), ("update", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("threads", ctypes.c_uint32), ("block", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("group", ctypes.c_uint32), ("ranges", ctypes.c_uint32), ("hubs", ctypes.c_uint32),
-                ("lds_kib", ctypes.c_uint32), ("eager_max", ctypes.c_uint32)]
+                ("lds_kib", ctypes.c_uint32), ("eager_max", ctypes.c_uint32), ("pack", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -68,7 +68,7 @@ class Stats(ctypes.Structure):
                 ("lds_chunk_words", ctypes.c_uint32), ("hub_cpos", ctypes.c_uint32),
                 ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32), ("kernel_vgprs", ctypes.c_uint32),
                 ("blocks_per_cu_runtime", ctypes.c_uint32), ("blocks_per_cu_own", ctypes.c_uint32),
-                ("eager_max", ctypes.c_uint32)]
+                ("eager_max", ctypes.c_uint32), ("packed", ctypes.c_int32)]
 
 
 _lib = None
@@ -175,7 +175,7 @@ class Graph:
 
     def __init__(self, csr, *, sigma=8, slots=2, window=1 << 16, reorder="auto", update="auto",
                  device=0, threads=0, block=0, blocks_per_cu=0, group=0, ranges=0, hubs="auto", lds_kib=0,
-                 eager_max=0):
+                 eager_max=0, pack=True):
         o = default_options()
         o.sigma, o.slots, o.window = sigma, slots, window
         o.reorder, o.update = REORDER[reorder], UPDATE[update]
@@ -183,6 +183,7 @@ class Graph:
         o.group, o.ranges, o.hubs = group, ranges, HUBS[hubs]
         o.lds_kib = LDS_OFF if lds_kib is None else lds_kib
         o.eager_max = eager_max
+        o.pack = 0 if pack else 1
         rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint32)
         col = np.ascontiguousarray(csr.col if len(csr.col) else np.zeros(1, np.uint32), dtype=np.uint32)
         h = ctypes.c_void_p()

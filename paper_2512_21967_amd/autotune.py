@@ -167,6 +167,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", required=True, choices=sorted(WORKLOADS))
     ap.add_argument("--repeats", type=int, default=3)
+    ap.add_argument("--out", default=TUNED_PATH, help="store to update (default: the package's tuned.json)")
     args = ap.parse_args()
     w = WORKLOADS[args.workload]
     if args.workload == "rmat22":
@@ -184,7 +185,7 @@ def main():
     log = lambda m: print(m, file=sys.stderr, flush=True)
     best, trials = autotune(gr, src, k=w["k"], cands=w["cands"], repeats=args.repeats, reorder=reorder, log=log)
     key = graph_key(gr, w["k"])
-    save(key, best, trials, args.workload)
+    save(key, best, trials, args.workload, path=args.out)
     print(json.dumps({"key": key, "best": best.options(), "ms": best.ms}), flush=True)
 
 

@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libblest.so")
-SOURCES = ["capi.cpp", "host.cpp", "kernels.hip", "kernels_multi.hip", "kernels_many.hip", "kernels_analytics.hip",
-           "kernels_serve.hip"]
+SOURCES = ["capi.cpp", "host.cpp", "kernels.hip", "kernels_eager.hip", "kernels_lazy.hip", "kernels_adaptive.hip",
+           "kernels_multi.hip", "kernels_many.hip", "kernels_analytics.hip", "kernels_serve.hip"]
 ARCH = os.environ.get("BLEST_OFFLOAD_ARCH", "gfx950")
 
 

@@ -90,7 +90,8 @@ struct blest_graph {
   // device state
   bool on_device = false;
   int device = -1;
-  DevBuf d_row_ids, d_masks, d_vss_beg, d_v2r, d_real_ptrs, d_orig_id, d_vss_range;
+  DevBuf d_row_ids, d_masks, d_vss_beg, d_v2r, d_real_ptrs, d_orig_id, d_vss_range, d_packed;
+  bool packed = false;  // the single-source kernel reads slices packed (sigma 8, row IDs < 2^24)
   uint32_t nranges = 1, range_len = 0, range_words = 0;
   uint32_t lds_cap_words = 0, lds_cshift = 0, hub_cpos = 0;
   uint32_t grid = 0, block = 0;
@@ -178,6 +179,7 @@ bool valid_options(const blest_options& o) {
   if (o.ranges > kMaxRanges || (o.ranges & (o.ranges - 1)) != 0) return false;
   if (o.hubs > 2) return false;
   if (o.lds_kib != BLEST_LDS_OFF && o.lds_kib > kMaxLdsBytes / 1024) return false;
+  if (o.pack > 1) return false;
   return true;
 }
 
@@ -226,6 +228,13 @@ blest_status to_device(blest_graph* g) {
     e = upload(g->d_orig_id, padded);
   }
   if (e == hipSuccess) e = upload(g->d_vss_range, b.vss_range);
+  // packed slices for the single-source kernel: row ID | mask << 24
+  g->packed = g->opt.pack == 0 && b.sigma == 8 && b.slots <= 4 && g->n <= (1u << 24);
+  if (e == hipSuccess && g->packed) {
+    std::vector<uint32_t> pk(b.num_slices);
+    for (uint64_t k = 0; k < b.num_slices; ++k) pk[k] = b.row_ids[k] | ((uint32_t)b.masks[k] << 24);
+    e = upload(g->d_packed, pk);
+  }
   if (e == hipErrorOutOfMemory) return BLEST_ERR_OUT_OF_MEMORY;
   if (e != hipSuccess) return BLEST_ERR_DEVICE;
   blest_status st = set_grid(g);
@@ -278,7 +287,7 @@ blest_status set_grid(blest_graph* g) {
     return BLEST_ERR_DEVICE;
   g->block = g->opt.block;
   const bool lds = g->mode != 0 && g->range_words > 0;
-  const void* k = bfs_kernel_symbol(b.sigma, b.slots, g->mode, g->opt.group, lds);
+  const void* k = bfs_kernel_symbol(b.sigma, b.slots, g->mode, g->opt.group, lds, g->packed);
   if (lds) {
     // the LDS cache takes what the device leaves beside the kernel's static LDS
     int max_lds = 0;
@@ -394,6 +403,7 @@ BfsParams base_params(const blest_graph* g) {
   p.num_vss = g->bvss.num_vss;
   p.qcap = std::max<uint32_t>(g->bvss.num_vss, 1);
   p.vss_range = g->d_vss_range.as<uint8_t>();
+  p.packed = g->packed ? g->d_packed.as<uint32_t>() : nullptr;
   p.nranges = g->nranges;
   p.range_len = g->range_len;
   p.range_words = g->mode != 0 ? g->range_words : 0;
@@ -462,6 +472,7 @@ void blest_default_options(blest_options* o) {
   o->hubs = 0;
   o->lds_kib = 0;
   o->eager_max = 0;
+  o->pack = 0;
 }
 
 blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, const uint32_t* col_idx,
@@ -853,7 +864,8 @@ blest_status blest_stats(blest_handle h, blest_stats_t* o) {
   o->nranges = h->nranges;
   o->range_len = h->range_len;
   o->bvss_device_bytes = b.num_slices * (4 + b.sigma / 8) + 4ull * (2ull * b.num_vss + 1) + b.num_vss +
-                         4ull * (b.num_sets + 1) + (h->identity ? 0 : 4ull * h->n);
+                         4ull * (b.num_sets + 1) + (h->identity ? 0 : 4ull * h->n) + (h->packed ? 4 * b.num_slices : 0);
+  o->packed = h->packed ? 1 : 0;
   o->bvss_bytes_table3 = b.num_slices * (4 + b.sigma / 8) + 4ull * (b.num_vss + b.num_sets);
   o->reorder_seconds = h->reorder_seconds;
   o->build_seconds = h->build_seconds;

@@ -25,6 +25,7 @@ struct BfsParams {
   const uint32_t* real_ptrs;
   const uint32_t* orig_id;  // new label -> original ID, 32 * n_words entries; nullptr = identity
   const uint8_t* vss_range; // row range of each VSS
+  const uint32_t* packed;   // sigma = 8: row ID | mask << 24 per slice (nullptr: separate arrays)
   // per-call workspace
   uint32_t* vis;            // visited bits, n_words
   uint8_t* mark;            // lazy: reached byte per vertex, 32 * n_words
@@ -59,7 +60,7 @@ hipError_t launch_bfs(const BfsParams& p, uint32_t sigma, uint32_t slots, int mo
                       uint32_t block, hipStream_t stream);
 
 // Returns the kernel symbol used by launch_bfs (for occupancy queries).
-const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, int mode, uint32_t group, bool lds);
+const void* bfs_kernel_symbol(uint32_t sigma, uint32_t slots, int mode, uint32_t group, bool lds, bool packed);
 
 // k-source BFS (k <= 64): per-vertex 64-bit frontier and visited words, bit j for
 // source j.

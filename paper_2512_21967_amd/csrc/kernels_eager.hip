@@ -1,0 +1,47 @@
+// Instantiates the eager variant of the persistent single-source BFS kernel
+// (bfs_kernel.hpp) for every slice width, slot count and group depth.
+#include "bfs_kernel.hpp"
+
+namespace blest {
+namespace {
+
+template <typename MT, int SLOTS, bool LDSVIS>
+const void* sym_group(uint32_t group) {
+  switch (group) {
+    case 1: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, kEager, 1, LDSVIS>);
+    case 2: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, kEager, 2, LDSVIS>);
+    case 4: return reinterpret_cast<const void*>(&bfs_persistent<MT, SLOTS, kEager, 4, LDSVIS>);
+    default: return nullptr;
+  }
+}
+
+template <typename MT, int SLOTS>
+const void* sym_pick(uint32_t group) {
+  return sym_group<MT, SLOTS, false>(group);
+}
+
+template <typename MT>
+const void* sym_slots(uint32_t slots, uint32_t group, bool with8) {
+  switch (slots) {
+    case 1: return sym_pick<MT, 1>(group);
+    case 2: return sym_pick<MT, 2>(group);
+    case 4: return sym_pick<MT, 4>(group);
+    case 8: return with8 ? sym_pick<MT, 8>(group) : nullptr;
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+const void* bfs_symbol_eager(uint32_t sigma, uint32_t slots, uint32_t group, bool packed) {
+  // the packed layout exists for sigma = 8 with up to 4 slots
+  if (packed) return sigma == 8 ? sym_slots<Packed8>(slots, group, false) : nullptr;
+  switch (sigma) {
+    case 8: return sym_slots<uint8_t>(slots, group, true);
+    case 16: return sym_slots<uint16_t>(slots, group, true);
+    case 32: return sym_slots<uint32_t>(slots, group, true);
+    default: return nullptr;
+  }
+}
+
+}  // namespace blest

@@ -11,8 +11,10 @@
 // queues.  Columns start at different iterations: a column admitted at iteration
 // a writes level i - a + 1 for the bits it gains in iteration i.
 //
-// Between iterations (the level boundary) one wavefront of workgroup 0 runs the
-// control step:
+// At the start of every iteration one wavefront of workgroup 0 runs the control
+// step while the other wavefronts run Stage 1 (so an iteration costs two grid
+// barriers); its admissions take effect at the level boundary after Stage 2, and
+// the admitted columns start with the next iteration:
 //   * columns that gained no bit in the last iteration are finished; a request
 //     whose columns have all finished is reported done in its mailbox slot (host
 //     memory), after a system-scope release so that its levels are visible;
@@ -83,7 +85,10 @@ __device__ void serve_control(const ServeParams& p, uint32_t it) {
     // it never fires when Stage 2 reports growth correctly)
     const uint32_t n = g == 0 ? p.g[0].n : g == 1 ? p.g[1].n : g == 2 ? p.g[2].n : p.g[3].n;
     const bool overdue = ((act >> lane) & 1ull) && it - st->col_start[g][lane] > n + 2;
-    const uint64_t fin = act & (~u64_of_lane0(&st->alive[g]) | __ballot(overdue));
+    // columns admitted by the previous control step start in this iteration: they
+    // have not had a Stage 2 yet
+    const uint64_t fresh = u64_of_lane0(&st->admitted[g]);
+    const uint64_t fin = act & ((~u64_of_lane0(&st->alive[g]) & ~fresh) | __ballot(overdue));
     if (!fin) continue;
     const bool mine = (fin >> lane) & 1ull;
     const uint32_t r = mine ? st->col_ticket[g][lane] % kServeRing : 0u;
@@ -178,7 +183,7 @@ __device__ void serve_control(const ServeParams& p, uint32_t it) {
         const uint32_t n = g == 0 ? p.g[0].n : g == 1 ? p.g[1].n : g == 2 ? p.g[2].n : p.g[3].n;
         st->col_out[g][lane] = ds->out + 4ull * rank * n;
         st->col_ticket[g][lane] = t;
-        st->col_start[g][lane] = it;
+        st->col_start[g][lane] = it + 1;  // first expanded by the next iteration's Stage 1
         st->adm_gc[n_admit + rank] = (g << 8) | lane;
         st->adm_src[n_admit + rank] = ds->src[rank];
       }
@@ -189,7 +194,7 @@ __device__ void serve_control(const ServeParams& p, uint32_t it) {
         st->remaining[r] = k;
         st->maxlev[r] = 0;
         ds->state = 2;
-        mb->slot[r].admit_iter = it;
+        mb->slot[r].admit_iter = it + 1;
         sys_store(&mb->slot[r].state, 2u);
       }
       __threadfence_block();
@@ -261,7 +266,7 @@ __device__ void serve_init_b(const ServeParams& p, uint32_t it) {
     G.touched[s] = 2;  // on the frontier
     reinterpret_cast<int32_t*>(st->col_out[g][c])[sorig(G, s)] = 0;
   }
-  // the VSS ranges of the sources' slice sets join the current queue, once per
+  // the VSS ranges of the sources' slice sets join the next iteration's queue, once per
   // distinct (graph, slice set): one wavefront per admitted column, which appends
   // unless an earlier admitted column names the same set
   const uint32_t wid = tid / kWave, nwv = nt / kWave, lane = lane_id();
@@ -278,9 +283,9 @@ __device__ void serve_init_b(const ServeParams& p, uint32_t it) {
     const ServeGraph& G = p.g[g];
     const uint32_t b = G.real_ptrs[ss], e = G.real_ptrs[ss + 1];
     uint32_t pos = 0;
-    if (lane == 0 && e > b) pos = atomicAdd(qlen_of(p, g, (it - 1) % 3), e - b);
+    if (lane == 0 && e > b) pos = atomicAdd(qlen_of(p, g, it % 3), e - b);
     pos = readlane(pos, 0);
-    uint32_t* qc = G.queue + ((it - 1) & 1) * G.qcap;
+    uint32_t* qc = G.queue + (it & 1) * G.qcap;
     for (uint32_t j = lane; j < e - b; j += kWave) qc[pos + j] = b + j;
   }
 }
@@ -473,30 +478,30 @@ __global__ __launch_bounds__(1024) void serve_persistent(ServeParams p) {
   uint32_t it = st->iter;  // written by the previous launch (or at creation)
   if (tid == 0) st->launches += 1;
   for (;; ++it) {
-    if (blockIdx.x == 0 && threadIdx.x < kWave) serve_control(p, it);
-    grid_barrier(ctrl);
-    if (st->exit) break;
     if (tid == 0)
       for (uint32_t g = 0; g < p.ngraphs; ++g)
         __hip_atomic_store(qlen_of(p, g, (it + 1) % 3), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t len[kServeMaxGraphs] = {0, 0, 0, 0};
+    uint32_t dense = 0;
+    for (uint32_t g = 0; g < p.ngraphs; ++g) {
+      len[g] = ld_relaxed(qlen_of(p, g, (it - 1) % 3));
+      if ((uint64_t)len[g] * kDenseFrac >= p.g[g].num_vss) dense |= 1u << g;
+    }
+    // the control wavefront first settles finished and new requests, then joins
+    // Stage 1 (whose queue it does not change)
+    if (blockIdx.x == 0 && threadIdx.x < kWave) serve_control(p, it);
+    serve_stage1<MT, SLOTS>(p, it, len, dense);
+    grid_barrier(ctrl);
+    if (st->exit) break;
+    for (uint32_t g = 0; g < p.ngraphs; ++g)
+      if (st->active[g]) serve_stage2<SIG>(p, g, it, (dense >> g) & 1u);
+    grid_barrier(ctrl);
     if (st->n_admit) {
       serve_init_a(p);
       grid_barrier(ctrl);
       serve_init_b<SIG>(p, it);
       grid_barrier(ctrl);
     }
-    uint32_t len[kServeMaxGraphs] = {0, 0, 0, 0};
-    uint32_t dense = 0, run = 0;
-    for (uint32_t g = 0; g < p.ngraphs; ++g) {
-      len[g] = ld_relaxed(qlen_of(p, g, (it - 1) % 3));
-      if ((uint64_t)len[g] * kDenseFrac >= p.g[g].num_vss) dense |= 1u << g;
-      if (st->active[g]) run |= 1u << g;
-    }
-    serve_stage1<MT, SLOTS>(p, it, len, dense);
-    grid_barrier(ctrl);
-    for (uint32_t g = 0; g < p.ngraphs; ++g)
-      if ((run >> g) & 1u) serve_stage2<SIG>(p, g, it, (dense >> g) & 1u);
-    grid_barrier(ctrl);
   }
 }
 

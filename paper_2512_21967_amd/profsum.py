@@ -31,7 +31,8 @@ CSRC = os.path.join(ROOT, "paper_2512_21967_amd", "csrc")
 # Sources that build the single-source kernel and everything it reads or is
 # launched with (host-side layout, options, launch shape); the other kernels live
 # in translation units of their own and cannot change its code or traffic.
-SINGLE_SOURCE_FILES = ("capi.cpp", "device_common.hpp", "host.cpp", "internal.hpp", "kernels.hip", "kernels.hpp")
+SINGLE_SOURCE_FILES = ("bfs_kernel.hpp", "capi.cpp", "device_common.hpp", "host.cpp", "internal.hpp", "kernels.hip",
+                       "kernels.hpp", "kernels_adaptive.hip", "kernels_eager.hip", "kernels_lazy.hip")
 
 
 def kernel_source_hash(files=None):
