@@ -17,6 +17,9 @@ Contents
   * ``oracle.reorder`` - JaccardWithWindows (Algorithm 1) step by step, the
     social-like test (Section 2.2.1) and reverse Cuthill-McKee with the tie rules
     listed in its docstring.
+  * ``oracle.prepass`` - the shingle ordering (min-hashes of out-neighbour sets,
+    SplitMix64 hash functions) that stands in for Gorder before Algorithm 1
+    (Section 2.2), and its composition with Algorithm 1.
 
 Graphs are duck-typed: any object with ``n``, ``row_ptr`` (uint32[n+1]) and ``col``
 (uint32[nnz]) holding sorted out-neighbour lists.
