@@ -198,11 +198,14 @@ def run_single(args):
     opts = dict(gopts, update=args.update)
     if tuned:
         opts.update(tuned)
-    g = blest.Graph(gr, device=0, ranges=args.ranges, **opts)
+    if args.window:
+        opts["window"] = args.window
+    g = blest.Graph(gr, device=0, ranges=args.ranges, prepass=args.prepass, **opts)
     st = g.stats()
     if tuned:
         log(f"[bench] tuned choice for {tuned_key}: {tuned}")
-    log(f"[bench] build {time.time() - t0:.1f}s: reorder {st['reorder_used']} ({st['reorder_seconds']:.1f}s), "
+    log(f"[bench] build {time.time() - t0:.1f}s: reorder {st['reorder_used']} ({st['reorder_seconds']:.1f}s, "
+        f"pre-pass {'on' if st['prepass_used'] else 'off'}), "
         f"update {st['update_used']}, compression {st['compression']:.3f}, VSS {st['num_vss']}, "
         f"ranges {st['nranges']}, slices {st['num_slices']}, U_div {st['u_div_paper']:.0f}, "
         f"grid {st['grid']}x{st['block']}")
@@ -267,7 +270,8 @@ def run_single(args):
         parity += f" ({len(sources) - checked} not checked)"
     config = {"workload": desc, "n": gr.n, "arcs": int(gr.nnz), "sources": len(sources), "update": st["update_used"],
               "sigma": st["sigma"], "tau": st["tau"], "ranges": st["nranges"], "grid": st["grid"],
-              "block": st["block"], "compression": round(st["compression"], 4),
+              "block": st["block"], "compression": round(st["compression"], 4), "num_vss": st["num_vss"],
+              "prepass": "shingle" if st["prepass_used"] else None, "window": opts.get("window"),
               "ms_per_bfs_mean": round(float(ms.mean()), 4), "ms_per_bfs_median": round(float(np.median(ms)), 4),
               "model_bytes_per_bfs": int(mb.mean()), "model_bytes_from": "oracle levels" if checked else "gpu levels",
               "eager_max": st["eager_max"] if st["update_used"] == "adaptive" else None, "group": opts.get("group", 2),
@@ -331,7 +335,7 @@ def batched_leg(args):
     gr = inputs.rmat_workload(20, 16, seed=1)
     srcs = inputs.sources(gr, seed=7, k=64, distinct=True)
     tuned_key, tuned = tuned_options(gr, 64, args)
-    g = blest.Graph(gr, reorder="none", device=0, **(tuned or {}))
+    g = blest.Graph(gr, reorder="none", device=0, multi_ranges=args.multi_ranges, **(tuned or {}))
     deg = gr.degrees()
     stream = torch.cuda.current_stream()
     out = torch.empty((64, gr.n), dtype=torch.int32, device="cuda")
@@ -350,16 +354,21 @@ def batched_leg(args):
     b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the comparison: the same sources as single-source launches, on the
+    # single-source kernel's own best build (the tuned k = 1 choice, else defaults)
+    _, tuned1 = tuned_options(gr, 1, args)
+    g1 = blest.Graph(gr, reorder="none", device=0, **(tuned1 or {}))
     one = torch.empty(gr.n, dtype=torch.int32, device="cuda")
     for s in srcs[:4]:
-        g.bfs(int(s), levels=one, stream=stream)
+        g1.bfs(int(s), levels=one, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(steps):
         for s in srcs:
-            g.bfs(int(s), levels=one, stream=stream)
+            g1.bfs(int(s), levels=one, stream=stream)
     torch.cuda.synchronize()
     seq = (time.perf_counter() - t1) / steps
+    g1.close()
     gteps = row_edges.sum() * steps / wall / 1e9
     seq_gteps = row_edges.sum() / seq / 1e9
     ms = a.elapsed_time(b) / steps
@@ -467,7 +476,7 @@ def run_multi(args):
     gr = inputs.rmat_workload(20, 16, seed=1)
     srcs = inputs.sources(gr, seed=7, k=64, distinct=True)
     tuned_key, tuned = tuned_options(gr, 64, args)
-    g = blest.Graph(gr, reorder="none", device=0, **(tuned or {}))
+    g = blest.Graph(gr, reorder="none", device=0, multi_ranges=args.multi_ranges, **(tuned or {}))
     deg = gr.degrees()
     out = torch.empty((64, gr.n), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -490,16 +499,20 @@ def run_multi(args):
         copy_calibration()
     ms = np.array([a.elapsed_time(b) for a, b in ev])
     gteps = row_edges.sum() * args.steps / wall / 1e9
-    # the comparison: the same 64 sources as 64 single-source launches
+    # the comparison: the same 64 sources as 64 single-source launches, on the
+    # single-source kernel's own best build (the tuned k = 1 choice, else defaults)
+    _, tuned1 = tuned_options(gr, 1, args)
+    g1 = blest.Graph(gr, reorder="none", device=0, **(tuned1 or {}))
     one = torch.empty(gr.n, dtype=torch.int32, device="cuda")
     for s in srcs[:4]:
-        g.bfs(int(s), levels=one, stream=stream)
+        g1.bfs(int(s), levels=one, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for s in srcs:
-        g.bfs(int(s), levels=one, stream=stream)
+        g1.bfs(int(s), levels=one, stream=stream)
     torch.cuda.synchronize()
     seq = time.perf_counter() - t1
+    g1.close()
     seq_gteps = row_edges.sum() / seq / 1e9
     # the analytics reduction over the launch's 64 x n levels (blest_level_stats)
     for _ in range(2):
@@ -598,6 +611,22 @@ def run_many(args):
         h.bfs(s, levels=o)
     torch.cuda.synchronize()
     seq = time.perf_counter() - t1
+    # the makespan bound: the largest item (by stored slices) alone in a one-item
+    # launch, timed the same way
+    big = max(range(len(graphs)), key=lambda i: handles[i].stats()["num_slices"])
+    solo = blest.Batch([handles[big]], [srcs[big]])
+    for _ in range(3):
+        solo.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        solo.run()
+    e1.record()
+    torch.cuda.synchronize()
+    solo_ms = e0.elapsed_time(e1) / 10
+    solo.close()
+    log(f"[bench] largest item ({graphs[big].name}, {graphs[big].n} vertices) alone: {solo_ms:.3f} ms")
     roof = roofline(model, ms.mean() / 1000.0, "many256/many")
     log(f"[bench] one replay: {ms.mean():.3f} ms, {gteps:.2f} GTEPS; 256 launches: {seq * 1000:.2f} ms "
         f"({edges / seq / 1e9:.2f} GTEPS)")
@@ -620,7 +649,9 @@ def run_many(args):
     config = {"workload": "256 R-MAT graphs, scale U{10..16}, edge factor U{8..32}, one source each, one "
                           "graph-captured launch", "graphs": 256, "sequential_launches_ms": round(seq * 1000, 3),
               "speedup_vs_sequential": round(seq * 1000 / ms.mean(), 2),
-              "ms_per_replay_mean": round(float(ms.mean()), 4)}
+              "ms_per_replay_mean": round(float(ms.mean()), 4), "largest_item": graphs[big].name,
+              "largest_item_alone_ms": round(solo_ms, 4),
+              "replay_over_largest_item": round(float(ms.mean()) / solo_ms, 3)}
     line(gteps, args, wall * 1000 / args.steps, "u32", config, roof, cpu, {"parity": parity})
     batch.close()
     for h in handles:
@@ -675,7 +706,8 @@ def serve_sweep(handles, graphs, rhos, nreq, budget, log_prefix="[bench]"):
     sweep = []
     for rho in rhos:
         trace = poisson_trace(int(rho * 1000) + 17, rho / service, nreq, names, src_of)
-        reqs = srv.run(trace, keep=False)
+        reqs = srv.run(trace, keep=False,
+                       progress=lambda d, n, rho=rho: log(f"{log_prefix} rho {rho}: {d}/{n} requests done"))
         s = summarize(reqs, edges_of)
         wait = np.array([r.submitted_at - r.arrival for r in reqs]) * 1000.0
         s.update({"rho": rho, "rate_per_s": round(rho / service, 2), "p50_host_wait_ms": float(np.percentile(wait, 50)),
@@ -763,6 +795,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg of the default workload")
     ap.add_argument("--serve-leg-requests", type=int, default=400)
     ap.add_argument("--no-tuned", action="store_true", help="ignore the autotuner's stored choices")
+    ap.add_argument("--window", type=int, default=0, help="Algorithm 1 window (0: the library default)")
+    ap.add_argument("--prepass", default="auto", choices=["auto", "off", "shingle"],
+                    help="locality pre-pass before Algorithm 1 (single-source workloads)")
+    ap.add_argument("--multi-ranges", type=int, default=0, help="row ranges of the k-source partition (0: library default)")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the k-source leg of the default workload")
     args = ap.parse_args()

@@ -97,6 +97,17 @@ typedef struct {
   uint32_t pack;       /* 0 = auto: with sigma 8, slots <= 4 and n <= 2^24 the single-source kernel
                           reads each slice as one 32-bit word (row ID | mask << 24, an extra
                           4 bytes per slice on the device); 1 = off */
+  uint32_t multi_ranges; /* k-source kernel: row ranges of its own VSS partition, a power of two
+                          <= 32 (0 = 1).  With R > 1 its VSSs are also cut at R row ranges and
+                          workgroup b pulls range b % R only, so that each XCD's L2 holds one
+                          range's visited pairs */
+  uint32_t prepass;    /* locality pre-pass before Algorithm 1 (Section 2.2 runs Gorder there): 0 = auto
+                          (off), 1 = off, 2 = shingle ordering (vertices sorted by min-hashes of their
+                          out-neighbour sets, Chierichetti et al., KDD 2009) */
+  uint32_t shingles;   /* min-hashes per vertex of the shingle ordering, 1..8 (0 = 2) */
+  uint64_t shingle_seed; /* seed of its hash functions: h_i(u) is output u + 1 of the SplitMix64 stream
+                          (Steele, Lea and Flood, OOPSLA 2014) seeded with output i + 1 of the stream
+                          seeded with shingle_seed (default 0x243F6A8885A308D3) */
 } blest_options;
 
 #define BLEST_LDS_OFF 0xFFFFFFFFu
@@ -132,6 +143,10 @@ typedef struct {
                                    the grid uses the smaller of the two and blocks_per_cu */
   uint32_t eager_max;           /* adaptive threshold in effect (queued VSSs) */
   int32_t packed;               /* 1 if the single-source kernel reads packed slices */
+  uint32_t multi_ranges;        /* row ranges of the k-source kernel's VSS partition */
+  uint32_t multi_num_vss;       /* VSSs of that partition */
+  int32_t prepass_used;         /* 1 if the shingle pre-pass ran before Algorithm 1 */
+  double prepass_seconds;       /* its host time (included in reorder_seconds) */
 } blest_stats_t;
 
 /* Fills *opt with the defaults listed above. */
@@ -299,8 +314,10 @@ enum {
   BLEST_EXPORT_ROW_IDS = 4,         /* uint32[num_slices], new labels */
   BLEST_EXPORT_MASKS = 5,           /* sigma/8 bytes per slice, little-endian, bit j = column j */
   BLEST_EXPORT_VSS_RANGE = 6,       /* uint8[num_vss]: row range of each VSS */
-  BLEST_EXPORT_ORDER_ID = 7         /* uint32[n]: label of each original vertex after the ordering
-                                       alone (Algorithm 1 or RCM), before the hub sort */
+  BLEST_EXPORT_ORDER_ID = 7,        /* uint32[n]: label of each original vertex after the ordering
+                                       alone (pre-pass and Algorithm 1, or RCM), before the hub sort */
+  BLEST_EXPORT_PREPASS_ID = 8       /* uint32[n]: label of each original vertex after the shingle
+                                       pre-pass alone (the identity when it did not run) */
 };
 blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t capacity_bytes,
                           uint64_t* size_bytes);
@@ -343,6 +360,14 @@ blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k
  * at least one barrier.  Synchronous; allocates a small control block.
  * Errors: INVALID_ARGUMENT, NO_DEVICE, DEVICE. */
 blest_status blest_barrier_probe(int32_t device, uint32_t block, uint32_t rounds, double* seconds_per_barrier);
+
+/* Releases the library's process-wide HIP objects once the work using them has
+ * finished: the per-device events that order persistent launches and the item
+ * tables of finished blest_bfs_many launches.  For an orderly exit while the HIP
+ * runtime is still up (the Python binding calls it at interpreter exit).  Handles
+ * built before the call can afterwards only be destroyed; handles built after it
+ * work normally. */
+void blest_shutdown(void);
 
 /* Releases the handle and its device memory.  NULL is ignored.  Must not be called
  * while work using the handle is still pending on a stream. */

@@ -8,6 +8,7 @@ the call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -20,19 +21,21 @@ BLEST_OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "invalid graph", 3: "too large", 4: "out of memory",
           5: "budget", 6: "device error", 7: "no device", 8: "internal error"}
 REORDER = {"auto": 0, "none": 1, "compression": 2, "bandwidth": 3}
+PREPASS = {"auto": 0, "off": 1, "shingle": 2}
 UPDATE = {"auto": 0, "eager": 1, "lazy": 2, "adaptive": 3}
 HUBS = {"auto": 0, "off": 1, "on": 2}
 LDS_OFF = 0xFFFFFFFF
 EXPORT = {"new_id": (0, np.uint32), "real_ptrs": (1, np.uint32), "virtual_to_real": (2, np.uint32),
           "vss_begin": (3, np.uint32), "row_ids": (4, np.uint32), "masks": (5, np.uint8),
-          "vss_range": (6, np.uint8), "order_id": (7, np.uint32)}
+          "vss_range": (6, np.uint8), "order_id": (7, np.uint32),
+          "prepass_id": (8, np.uint32)}
 EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_bfs_noalloc", "blest_bfs_multi",
                     "blest_bfs_many",
                     "blest_batch_create", "blest_batch_run", "blest_batch_destroy", "blest_server_create",
                     "blest_server_submit", "blest_server_poll", "blest_server_release", "blest_server_stats",
                     "blest_server_destroy", "blest_configure", "blest_stats", "blest_footprint", "blest_export",
-                    "blest_model_bytes", "blest_level_stats", "blest_barrier_probe", "blest_destroy",
-                    "blest_status_string")
+                    "blest_model_bytes", "blest_level_stats", "blest_barrier_probe", "blest_shutdown",
+                    "blest_destroy", "blest_status_string")
 
 
 class ServerStats(ctypes.Structure):
@@ -52,7 +55,9 @@ class Options(ctypes.Structure):
                 ("reorder", ctypes.c_int32), ("update", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("threads", ctypes.c_uint32), ("block", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("group", ctypes.c_uint32), ("ranges", ctypes.c_uint32), ("hubs", ctypes.c_uint32),
-                ("lds_kib", ctypes.c_uint32), ("eager_max", ctypes.c_uint32), ("pack", ctypes.c_uint32)]
+                ("lds_kib", ctypes.c_uint32), ("eager_max", ctypes.c_uint32), ("pack", ctypes.c_uint32),
+                ("multi_ranges", ctypes.c_uint32), ("prepass", ctypes.c_uint32), ("shingles", ctypes.c_uint32),
+                ("shingle_seed", ctypes.c_uint64)]
 
 
 class Stats(ctypes.Structure):
@@ -68,7 +73,9 @@ class Stats(ctypes.Structure):
                 ("lds_chunk_words", ctypes.c_uint32), ("hub_cpos", ctypes.c_uint32),
                 ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32), ("kernel_vgprs", ctypes.c_uint32),
                 ("blocks_per_cu_runtime", ctypes.c_uint32), ("blocks_per_cu_own", ctypes.c_uint32),
-                ("eager_max", ctypes.c_uint32), ("packed", ctypes.c_int32)]
+                ("eager_max", ctypes.c_uint32), ("packed", ctypes.c_int32), ("multi_ranges", ctypes.c_uint32),
+                ("multi_num_vss", ctypes.c_uint32), ("prepass_used", ctypes.c_int32),
+                ("prepass_seconds", ctypes.c_double)]
 
 
 _lib = None
@@ -82,6 +89,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         from . import build as _build
         _build.build()
+    # PyTorch ships its own HIP runtime under the same soname as the system one; it
+    # has to be the one in the process (loaded first), or a later torch.cuda call
+    # runs on the other copy and finds no GPU
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
     p32 = ctypes.POINTER(ctypes.c_uint32)
@@ -129,11 +143,15 @@ def lib():
     L.blest_level_stats.restype = ctypes.c_int
     L.blest_barrier_probe.argtypes = [i32, u32, u32, ctypes.POINTER(ctypes.c_double)]
     L.blest_barrier_probe.restype = ctypes.c_int
+    L.blest_shutdown.argtypes = []
+    L.blest_shutdown.restype = None
     L.blest_destroy.argtypes = [vp]
     L.blest_destroy.restype = None
     L.blest_status_string.argtypes = [ctypes.c_int]
     L.blest_status_string.restype = ctypes.c_char_p
     _lib = L
+    # the library's process-wide HIP objects go while the runtime is still up
+    atexit.register(L.blest_shutdown)
     return L
 
 
@@ -175,7 +193,7 @@ class Graph:
 
     def __init__(self, csr, *, sigma=8, slots=2, window=1 << 16, reorder="auto", update="auto",
                  device=0, threads=0, block=0, blocks_per_cu=0, group=0, ranges=0, hubs="auto", lds_kib=0,
-                 eager_max=0, pack=True):
+                 eager_max=0, pack=True, multi_ranges=0, prepass="auto", shingles=0, shingle_seed=None):
         o = default_options()
         o.sigma, o.slots, o.window = sigma, slots, window
         o.reorder, o.update = REORDER[reorder], UPDATE[update]
@@ -184,6 +202,10 @@ class Graph:
         o.lds_kib = LDS_OFF if lds_kib is None else lds_kib
         o.eager_max = eager_max
         o.pack = 0 if pack else 1
+        o.multi_ranges = multi_ranges
+        o.prepass, o.shingles = PREPASS[prepass], shingles
+        if shingle_seed is not None:
+            o.shingle_seed = shingle_seed
         rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint32)
         col = np.ascontiguousarray(csr.col if len(csr.col) else np.zeros(1, np.uint32), dtype=np.uint32)
         h = ctypes.c_void_p()

@@ -79,6 +79,9 @@ struct blest_graph {
   Bvss bvss;
   std::vector<uint32_t> new_id;   // original -> new
   std::vector<uint32_t> order_id; // original -> label after the ordering alone (before the hub sort)
+  std::vector<uint32_t> prepass_id; // original -> label after the shingle pre-pass alone (empty: none)
+  int prepass_used = 0;
+  double prepass_seconds = 0;
   std::vector<uint32_t> orig_id;  // new -> original
   bool identity = true;
   int mode = 0;  // kernel scheme: 0 eager (Algorithm 2), 1 lazy (Algorithm 3), 2 adaptive per level
@@ -92,6 +95,11 @@ struct blest_graph {
   int device = -1;
   DevBuf d_row_ids, d_masks, d_vss_beg, d_v2r, d_real_ptrs, d_orig_id, d_vss_range, d_packed;
   bool packed = false;  // the single-source kernel reads slices packed (sigma 8, row IDs < 2^24)
+  // The k-source kernel's own VSS partition, cut at multi_ranges row ranges (used
+  // when multi_ranges > 1; the slices are shared with the base partition).
+  uint32_t multi_ranges = 1;
+  VssPartition mpart;
+  DevBuf d_m_real_ptrs, d_m_v2r, d_m_vss_beg, d_m_vss_range;
   uint32_t nranges = 1, range_len = 0, range_words = 0;
   uint32_t lds_cap_words = 0, lds_cshift = 0, hub_cpos = 0;
   uint32_t grid = 0, block = 0;
@@ -180,6 +188,8 @@ bool valid_options(const blest_options& o) {
   if (o.hubs > 2) return false;
   if (o.lds_kib != BLEST_LDS_OFF && o.lds_kib > kMaxLdsBytes / 1024) return false;
   if (o.pack > 1) return false;
+  if (o.multi_ranges > kMaxRanges || (o.multi_ranges & (o.multi_ranges - 1)) != 0) return false;
+  if (o.prepass > 2 || o.shingles > 8) return false;
   return true;
 }
 
@@ -228,6 +238,10 @@ blest_status to_device(blest_graph* g) {
     e = upload(g->d_orig_id, padded);
   }
   if (e == hipSuccess) e = upload(g->d_vss_range, b.vss_range);
+  if (e == hipSuccess && g->multi_ranges > 1) e = upload(g->d_m_real_ptrs, g->mpart.real_ptrs);
+  if (e == hipSuccess && g->multi_ranges > 1) e = upload(g->d_m_v2r, g->mpart.v2r);
+  if (e == hipSuccess && g->multi_ranges > 1) e = upload(g->d_m_vss_beg, g->mpart.vss_beg);
+  if (e == hipSuccess && g->multi_ranges > 1) e = upload(g->d_m_vss_range, g->mpart.vss_range);
   // packed slices for the single-source kernel: row ID | mask << 24
   g->packed = g->opt.pack == 0 && b.sigma == 8 && b.slots <= 4 && g->n <= (1u << 24);
   if (e == hipSuccess && g->packed) {
@@ -317,7 +331,8 @@ blest_status set_grid(blest_graph* g) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbm, km, (int)g->block, 0) != hipSuccess || nbm <= 0)
     return BLEST_ERR_DEVICE;
   const uint32_t own_m = own_blocks_per_cu(km, g->block, 0, &regs_m);
-  g->multi_grid = std::min({(uint32_t)nbm, own_m, g->opt.blocks_per_cu}) * (uint32_t)cus;
+  g->multi_grid = std::min({(uint32_t)nbm, own_m, g->opt.blocks_per_cu}) * (uint32_t)cus / g->multi_ranges *
+                  g->multi_ranges;
   if (g->multi_grid == 0) return BLEST_ERR_DEVICE;
   return BLEST_OK;
 }
@@ -354,7 +369,8 @@ MultiWorkspace* multi_workspace(blest_graph* g, void* stream, blest_status* st) 
   hipError_t e = ws->vis.alloc(16 * n);
   if (e == hipSuccess) e = ws->front.alloc(8 * n);
   if (e == hipSuccess) e = ws->touched.alloc((size_t)std::max<uint32_t>(g->bvss.num_sets, 1) * g->bvss.sigma);
-  if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 2 * std::max<size_t>(g->bvss.num_vss, 1));
+  const size_t qv = std::max<size_t>(g->multi_ranges > 1 ? g->mpart.num_vss : g->bvss.num_vss, 1);
+  if (e == hipSuccess) e = ws->queue.alloc(sizeof(uint32_t) * 2 * qv);
   if (e == hipSuccess) e = ws->ctrl.alloc(sizeof(uint32_t) * kCtrlWords);
   if (e == hipSuccess) e = hipMemset(ws->ctrl.p, 0, sizeof(uint32_t) * kCtrlWords);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -473,6 +489,10 @@ void blest_default_options(blest_options* o) {
   o->lds_kib = 0;
   o->eager_max = 0;
   o->pack = 0;
+  o->multi_ranges = 0;
+  o->prepass = 0;
+  o->shingles = 0;
+  o->shingle_seed = 0x243F6A8885A308D3ull;
 }
 
 blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, const uint32_t* col_idx,
@@ -511,7 +531,20 @@ blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, cons
     } else {
       Csr gt;
       transpose(csr, gt);
-      if (reorder == BLEST_REORDER_COMPRESSION) {
+      if (reorder == BLEST_REORDER_COMPRESSION && o.prepass == 2) {
+        // shingle pre-pass, then Algorithm 1's windows over the pre-pass labels
+        const double tp = now_s();
+        shingle_order(csr, o.shingles ? o.shingles : 2, o.shingle_seed, T, g->prepass_id);
+        Csr pre, pret;
+        relabel(csr, g->prepass_id, T, pre);
+        transpose(pre, pret);
+        g->prepass_used = 1;
+        g->prepass_seconds = now_s() - tp;
+        std::vector<uint32_t> win_id;
+        jaccard_windows(pre, pret, o.sigma, o.window, T, win_id);
+        g->new_id.resize(n);
+        for (uint32_t v = 0; v < n; ++v) g->new_id[v] = win_id[g->prepass_id[v]];
+      } else if (reorder == BLEST_REORDER_COMPRESSION) {
         jaccard_windows(csr, gt, o.sigma, o.window, T, g->new_id);
       } else {
         Csr und;
@@ -569,6 +602,12 @@ blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, cons
     rc = partition_vss(g->bvss, R > 1 ? g->range_len : 0, T);
     if (rc != kOk) return map_rc(rc);
     if (g->bvss.num_vss >= (1u << (32 - kRangeBits))) return BLEST_ERR_TOO_LARGE;
+    g->multi_ranges = o.multi_ranges ? o.multi_ranges : 1;
+    if (g->multi_ranges > 1) {
+      const uint32_t rwm = (nw + g->multi_ranges - 1) / g->multi_ranges;
+      partition_vss_into(g->bvss, rwm * 32, T, g->mpart);
+      if (g->mpart.num_vss >= (1u << (32 - kRangeBits))) return BLEST_ERR_TOO_LARGE;
+    }
     g->build_seconds = now_s() - t1;
     g->u_div_native = update_divergence(g->bvss, 64, 0);
     if (o.device >= 0) {
@@ -670,11 +709,14 @@ blest_status blest_bfs_multi(blest_handle h, const uint32_t* sources, uint32_t k
     MultiWorkspace* ws = multi_workspace(h, stream, &st);
     if (!ws) return st;
     MultiParams p{};
+    const bool mr = h->multi_ranges > 1;
     p.row_ids = h->d_row_ids.as<uint32_t>();
     p.masks = h->d_masks.p;
-    p.vss_beg = h->d_vss_beg.as<uint32_t>();
-    p.v2r = h->d_v2r.as<uint32_t>();
-    p.real_ptrs = h->d_real_ptrs.as<uint32_t>();
+    p.vss_beg = (mr ? h->d_m_vss_beg : h->d_vss_beg).as<uint32_t>();
+    p.v2r = (mr ? h->d_m_v2r : h->d_v2r).as<uint32_t>();
+    p.real_ptrs = (mr ? h->d_m_real_ptrs : h->d_real_ptrs).as<uint32_t>();
+    p.vss_range = mr ? h->d_m_vss_range.as<uint8_t>() : nullptr;
+    p.nranges = h->multi_ranges;
     p.orig_id = h->identity ? nullptr : h->d_orig_id.as<uint32_t>();
     p.vis = ws->vis.as<unsigned long long>();
     p.front = ws->front.as<unsigned long long>();
@@ -684,8 +726,8 @@ blest_status blest_bfs_multi(blest_handle h, const uint32_t* sources, uint32_t k
     p.levels = levels_out;
     p.n = h->n;
     p.num_sets = h->bvss.num_sets;
-    p.num_vss = h->bvss.num_vss;
-    p.qcap = std::max<uint32_t>(h->bvss.num_vss, 1);
+    p.num_vss = mr ? h->mpart.num_vss : h->bvss.num_vss;
+    p.qcap = std::max<uint32_t>(p.num_vss, 1);
     p.k = k;
     for (uint32_t j = 0; j < k; ++j) {
       p.src[j] = h->new_id[sources[j]];
@@ -866,8 +908,12 @@ blest_status blest_stats(blest_handle h, blest_stats_t* o) {
   o->bvss_device_bytes = b.num_slices * (4 + b.sigma / 8) + 4ull * (2ull * b.num_vss + 1) + b.num_vss +
                          4ull * (b.num_sets + 1) + (h->identity ? 0 : 4ull * h->n) + (h->packed ? 4 * b.num_slices : 0);
   o->packed = h->packed ? 1 : 0;
+  o->multi_ranges = h->multi_ranges;
+  o->multi_num_vss = h->multi_ranges > 1 ? h->mpart.num_vss : b.num_vss;
   o->bvss_bytes_table3 = b.num_slices * (4 + b.sigma / 8) + 4ull * (b.num_vss + b.num_sets);
   o->reorder_seconds = h->reorder_seconds;
+  o->prepass_used = h->prepass_used;
+  o->prepass_seconds = h->prepass_seconds;
   o->build_seconds = h->build_seconds;
   o->hubs_sorted = h->hubs_sorted;
   o->grid = h->grid;
@@ -915,6 +961,14 @@ blest_status blest_export(blest_handle h, int32_t which, void* dst, uint64_t cap
     case BLEST_EXPORT_MASKS: src = b.masks.data(); bytes = b.masks.size(); break;
     case BLEST_EXPORT_VSS_RANGE: src = b.vss_range.data(); bytes = b.vss_range.size(); break;
     case BLEST_EXPORT_ORDER_ID: src = h->order_id.data(); bytes = 4ull * h->order_id.size(); break;
+    case BLEST_EXPORT_PREPASS_ID:
+      if (h->prepass_id.empty()) {  // identity
+        h->prepass_id.resize(h->n);
+        for (uint32_t v = 0; v < h->n; ++v) h->prepass_id[v] = v;
+      }
+      src = h->prepass_id.data();
+      bytes = 4ull * h->prepass_id.size();
+      break;
     default: return BLEST_ERR_INVALID_ARGUMENT;
   }
   *size = bytes;
@@ -1260,6 +1314,26 @@ blest_status blest_barrier_probe(int32_t device, uint32_t block, uint32_t rounds
   if (e != hipSuccess) return BLEST_ERR_DEVICE;
   *seconds_per_barrier = ms[1] / 1000.0 / rounds;
   return BLEST_OK;
+}
+
+void blest_shutdown(void) {
+  {
+    std::lock_guard<std::mutex> lk(g_pending_mu);
+    for (PendingBatch& pb : g_pending) {
+      (void)hipEventSynchronize(pb.done);
+      (void)hipEventDestroy(pb.done);
+      blest_batch_destroy(pb.b);
+    }
+    g_pending.clear();
+  }
+  for (int d = 0; d < 64; ++d) {
+    DeviceSerial& ds = g_serial[d];
+    std::lock_guard<std::mutex> lk(ds.mu);
+    if (!ds.last) continue;
+    (void)hipEventSynchronize(ds.last);
+    (void)hipEventDestroy(ds.last);
+    ds.last = nullptr;
+  }
 }
 
 void blest_destroy(blest_handle h) {

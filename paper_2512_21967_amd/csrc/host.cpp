@@ -297,6 +297,46 @@ void jaccard_windows(const Csr& g, const Csr& gt, uint32_t sigma, uint32_t w, in
 // minimum-(degree, ID) vertex of the last BFS level while the eccentricity grows;
 // neighbours are enqueued in (degree, ID) order; the whole order is reversed.
 // ---------------------------------------------------------------------------
+uint64_t splitmix64(uint64_t seed, uint64_t t) {
+  uint64_t z = seed + t * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void shingle_order(const Csr& g, uint32_t hashes, uint64_t seed, int threads, std::vector<uint32_t>& new_id) {
+  const uint32_t n = g.n, k = hashes;
+  std::vector<uint64_t> s(k);
+  for (uint32_t i = 0; i < k; ++i) s[i] = splitmix64(seed, i + 1);
+  // h_i(u) for every vertex, then each row's minimum per hash
+  std::vector<uint64_t> h((size_t)n * k), key((size_t)n * k);
+  parallel_chunks(n, 1 << 14, threads, [&](uint64_t lo, uint64_t hi) {
+    for (uint64_t u = lo; u < hi; ++u)
+      for (uint32_t i = 0; i < k; ++i) h[u * k + i] = splitmix64(s[i], u + 1);
+  });
+  parallel_chunks(n, 1 << 12, threads, [&](uint64_t lo, uint64_t hi) {
+    for (uint64_t v = lo; v < hi; ++v) {
+      uint64_t* kv = key.data() + v * k;
+      for (uint32_t i = 0; i < k; ++i) kv[i] = ~0ull;
+      for (uint32_t a = g.rp[v]; a < g.rp[v + 1]; ++a) {
+        const uint64_t* hu = h.data() + (uint64_t)g.col[a] * k;
+        for (uint32_t i = 0; i < k; ++i) kv[i] = std::min(kv[i], hu[i]);
+      }
+    }
+  });
+  std::vector<uint32_t> order(n);
+  std::iota(order.begin(), order.end(), 0u);
+  std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+    const uint64_t* ka = key.data() + (uint64_t)a * k;
+    const uint64_t* kb = key.data() + (uint64_t)b * k;
+    for (uint32_t i = 0; i < k; ++i)
+      if (ka[i] != kb[i]) return ka[i] < kb[i];
+    return a < b;
+  });
+  new_id.assign(n, 0);
+  for (uint32_t r = 0; r < n; ++r) new_id[order[r]] = r;
+}
+
 void rcm(const Csr& u, std::vector<uint32_t>& new_id) {
   const uint32_t n = u.n;
   auto deg = [&](uint32_t v) { return u.rp[v + 1] - u.rp[v]; };
@@ -444,11 +484,11 @@ int build_slices(const Csr& g, uint32_t sigma, uint32_t slots, int threads, Bvss
   return kOk;
 }
 
-int partition_vss(Bvss& b, uint32_t range_len, int threads) {
+void partition_vss_into(const Bvss& b, uint32_t range_len, int threads, VssPartition& out) {
   const uint32_t S = b.num_sets;
   // VSS partition: cut each set's row-sorted slices into runs of at most tau that
   // also stay inside one row range of range_len IDs (no range split if 0).
-  b.range_len = range_len;
+  out.range_len = range_len;
   auto range_of = [&](uint32_t row) { return range_len ? row / range_len : 0u; };
   auto walk = [&](uint32_t s, auto&& emit) {
     uint32_t k = b.set_beg[s], e = b.set_beg[s + 1];
@@ -464,24 +504,35 @@ int partition_vss(Bvss& b, uint32_t range_len, int threads) {
   parallel_chunks(S, 4096, threads, [&](uint64_t lo, uint64_t hi) {
     for (uint64_t s = lo; s < hi; ++s) walk((uint32_t)s, [&](uint32_t, uint32_t) { ++vss_cnt[s]; });
   });
-  b.real_ptrs.assign((size_t)S + 1, 0);
-  for (uint32_t s = 0; s < S; ++s) b.real_ptrs[s + 1] = b.real_ptrs[s] + vss_cnt[s];
-  b.num_vss = b.real_ptrs[S];
-  b.v2r.resize(b.num_vss);
-  b.vss_beg.resize((size_t)b.num_vss + 1);
-  b.vss_range.resize(b.num_vss);
+  out.real_ptrs.assign((size_t)S + 1, 0);
+  for (uint32_t s = 0; s < S; ++s) out.real_ptrs[s + 1] = out.real_ptrs[s] + vss_cnt[s];
+  out.num_vss = out.real_ptrs[S];
+  out.v2r.resize(out.num_vss);
+  out.vss_beg.resize((size_t)out.num_vss + 1);
+  out.vss_range.resize(out.num_vss);
   parallel_chunks(S, 4096, threads, [&](uint64_t lo, uint64_t hi) {
     for (uint64_t s = lo; s < hi; ++s) {
-      uint32_t v = b.real_ptrs[s];
+      uint32_t v = out.real_ptrs[s];
       walk((uint32_t)s, [&](uint32_t k, uint32_t r) {
-        b.v2r[v] = (uint32_t)s;
-        b.vss_beg[v] = k;
-        b.vss_range[v] = (uint8_t)r;
+        out.v2r[v] = (uint32_t)s;
+        out.vss_beg[v] = k;
+        out.vss_range[v] = (uint8_t)r;
         ++v;
       });
     }
   });
-  b.vss_beg[b.num_vss] = (uint32_t)b.num_slices;
+  out.vss_beg[out.num_vss] = (uint32_t)b.num_slices;
+}
+
+int partition_vss(Bvss& b, uint32_t range_len, int threads) {
+  VssPartition part;
+  partition_vss_into(b, range_len, threads, part);
+  b.range_len = part.range_len;
+  b.num_vss = part.num_vss;
+  b.real_ptrs = std::move(part.real_ptrs);
+  b.v2r = std::move(part.v2r);
+  b.vss_beg = std::move(part.vss_beg);
+  b.vss_range = std::move(part.vss_range);
   return kOk;
 }
 

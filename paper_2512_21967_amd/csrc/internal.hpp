@@ -38,6 +38,17 @@ bool social_like(const Csr& g);
 void jaccard_windows(const Csr& g, const Csr& gt, uint32_t sigma, uint32_t w, int threads,
                      std::vector<uint32_t>& new_id);
 
+// Shingle ordering (Chierichetti et al., "On compressing social networks", KDD
+// 2009), the locality pre-pass run before Algorithm 1 in place of Gorder
+// (Section 2.2 names Gorder without specifying it): vertex v gets the key
+// (min over out-neighbours u of h_0(u), ..., of h_{k-1}(u)) and vertices take labels
+// in ascending key order, ties by ID; no out-neighbours: every component is
+// 2^64 - 1.  h_i(u) is output u + 1 of the SplitMix64 stream (Steele, Lea and
+// Flood, OOPSLA 2014) seeded with s_i, and s_i is output i + 1 of the stream
+// seeded with `seed`.  Output: new_id.
+void shingle_order(const Csr& g, uint32_t hashes, uint64_t seed, int threads, std::vector<uint32_t>& new_id);
+uint64_t splitmix64(uint64_t seed, uint64_t t);  // output t (t >= 1) of the stream seeded with seed
+
 // Reverse Cuthill-McKee on the undirected view u.  Output: new_id.
 void rcm(const Csr& u, std::vector<uint32_t>& new_id);
 
@@ -84,9 +95,18 @@ struct Bvss {
   }
 };
 
+// A VSS partition of a Bvss's slices (the arrays of the same names in Bvss).
+struct VssPartition {
+  uint32_t num_vss = 0, range_len = 0;
+  std::vector<uint32_t> real_ptrs, v2r, vss_beg;
+  std::vector<uint8_t> vss_range;
+};
+
 // Slices of every set (set_beg, row_ids, masks); then the VSS partition.
 int build_slices(const Csr& g, uint32_t sigma, uint32_t slots, int threads, Bvss& out);
 int partition_vss(Bvss& b, uint32_t range_len, int threads);
+// The same partition into separate arrays (b is not changed).
+void partition_vss_into(const Bvss& b, uint32_t range_len, int threads, VssPartition& out);
 
 // Update divergence (Section 2.2.1) when each set's sorted slices are cut into
 // VSSs of lanes * slots_per_lane and columns of `lanes` consecutive slices;

@@ -78,6 +78,8 @@ struct MultiParams {
   uint32_t* queue;                // 2 * qcap
   uint32_t* ctrl;                 // kCtrlWords
   int32_t* levels;                // k * n, original IDs, row j for source j
+  const uint8_t* vss_range;        // row range of each VSS (nullptr when nranges == 1)
+  uint32_t nranges;                // row ranges of this kernel's VSS partition (grid is a multiple)
   uint32_t n, num_sets, num_vss, qcap, k, n_init_sets;
   uint32_t src[kMaxSources];       // new labels
   uint32_t init_sets[kMaxSources]; // distinct slice sets holding a source

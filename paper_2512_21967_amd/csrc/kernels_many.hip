@@ -61,27 +61,46 @@ __global__ __launch_bounds__(kManyBlock) void bfs_many_kernel(const ManyItem* __
     uint32_t* qn = it.queue + (level & 1) * qcap;
     const uint32_t len = s_qlen[(level - 1) & 1];
     // ---- Stage 1: wavefronts take VSSs round-robin; marks go to LDS ----
-    for (uint32_t q = wave; q < len; q += nwaves) {
-      const uint32_t v = qc[q];
-      const uint32_t beg = it.vss_beg[v], end = it.vss_beg[v + 1];
-      const uint32_t ss = it.v2r[v];
-      const uint32_t bitpos = ss * SIG;
-      const uint32_t alpha = (front[bitpos >> 5] >> (bitpos & 31)) & (SIG == 32 ? 0xFFFFFFFFu : ((1u << SIG) - 1u));
-      MT m[SLOTS];
-      uint32_t u[SLOTS];
-#pragma unroll
-      for (int r = 0; r < SLOTS; ++r) {
-        const uint32_t idx = beg + lane + r * kWave;
-        const bool ok = idx < end;
-        m[r] = ok ? masks[idx] : MT(0);
-        u[r] = ok ? it.row_ids[idx] : 0u;
+    // Lane l first fetches the queue entry, slice range and frontier chunk of the
+    // wavefront's l-th next VSS, so the dependent entry -> metadata loads are paid
+    // once per 64 VSSs (values broadcast with readlane); the slice loads of two
+    // VSSs are then issued before either is applied.
+    for (uint32_t base = wave; base < len; base += nwaves * kWave) {
+      const uint32_t pos = base + lane * nwaves;
+      uint32_t mb = 0, me = 0, ma = 0;
+      if (pos < len) {
+        const uint32_t v = qc[pos];
+        mb = it.vss_beg[v];
+        me = it.vss_beg[v + 1];
+        const uint32_t bitpos = it.v2r[v] * SIG;
+        ma = (front[bitpos >> 5] >> (bitpos & 31)) & (SIG == 32 ? 0xFFFFFFFFu : ((1u << SIG) - 1u));
       }
+      const uint32_t cnt = min((uint32_t)kWave, (len - base + nwaves - 1) / nwaves);
+      for (uint32_t k = 0; k < cnt; k += 2) {
+        MT m[2][SLOTS];
+        uint32_t u[2][SLOTS], alpha[2];
 #pragma unroll
-      for (int r = 0; r < SLOTS; ++r) {
-        if ((uint32_t)m[r] & alpha) {
-          const uint32_t w = u[r] >> 5, bit = 1u << (u[r] & 31);
-          if (!((vis[2 * w] | vis[2 * w + 1]) & bit)) atomicOr(&vis[2 * w + 1], bit);
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t src = k + h < cnt ? k + h : k;
+          const uint32_t beg = readlane(mb, src), end = k + h < cnt ? readlane(me, src) : beg;
+          alpha[h] = readlane(ma, src);
+#pragma unroll
+          for (int r = 0; r < SLOTS; ++r) {
+            const uint32_t idx = beg + lane + r * kWave;
+            const bool ok = idx < end;
+            m[h][r] = ok ? masks[idx] : MT(0);
+            u[h][r] = ok ? it.row_ids[idx] : 0u;
+          }
         }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < SLOTS; ++r) {
+            if ((uint32_t)m[h][r] & alpha[h]) {
+              const uint32_t w = u[h][r] >> 5, bit = 1u << (u[h][r] & 31);
+              if (!((vis[2 * w] | vis[2 * w + 1]) & bit)) atomicOr(&vis[2 * w + 1], bit);
+            }
+          }
       }
     }
     if (threadIdx.x == 0) s_qlen[level & 1] = 0;

@@ -28,62 +28,106 @@ constexpr uint64_t kDenseFrac = 16;
 
 __device__ __forceinline__ uint32_t morig(const MultiParams& p, uint32_t u) { return p.orig_id ? p.orig_id[u] : u; }
 
+// Queue entry of VSS v: (v << kRangeBits) | its row range.
+struct MultiEntry {
+  const uint8_t* vss_range;  // nullptr: one range
+  __device__ uint32_t operator()(uint32_t v, uint32_t) const {
+    return vss_range ? (v << kRangeBits) | vss_range[v] : v << kRangeBits;
+  }
+};
+
+// Stage 1.  With p.nranges = R > 1 every VSS pulls rows of one row range only,
+// and workgroup b serves range b % R: wavefronts scan the queue in strides of the
+// range group's wavefront count and take the entries of their range.  Workgroups
+// are dealt to the 8 XCDs round-robin, so with R = 8 the rows of a range, and
+// their visited pairs, are pulled, read and ORed from one XCD, whose L2 holds
+// that range's share of the pairs.
 template <typename MT, int SLOTS>
 __device__ __forceinline__ void multi_stage1(const MultiParams& p, const uint32_t* qc, uint32_t len, bool mark) {
   constexpr int SIG = 8 * sizeof(MT);
   const MT* masks = static_cast<const MT*>(p.masks);
   const uint32_t lane = lane_id();
-  const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const uint32_t nw = (gridDim.x * blockDim.x) / kWave;
+  const uint32_t R = p.nranges, rg = blockIdx.x % R;
+  const uint32_t W = blockDim.x / kWave;
+  const uint32_t wid = (blockIdx.x / R) * W + threadIdx.x / kWave;
+  const uint32_t nw = (gridDim.x / R) * W;
   for (uint32_t base = wid; base < len; base += nw * kWave) {
     // lane l stages the metadata of this wavefront's l-th next queue position
     const uint32_t pos = base + lane * nw;
+    const uint32_t e = pos < len ? qc[pos] : 0u;
+    const bool mine = pos < len && (e & (kMaxRanges - 1)) == rg;
     uint32_t mb = 0, me = 0, ms = 0;
-    if (pos < len) {
-      const uint32_t v = qc[pos];
+    if (mine) {
+      const uint32_t v = e >> kRangeBits;
       mb = p.vss_beg[v];
       me = p.vss_beg[v + 1];
       ms = p.v2r[v];
     }
-    const uint32_t cnt = min((uint32_t)kWave, (len - base + nw - 1) / nw);
-    for (uint32_t k = 0; k < cnt; ++k) {
-      const uint32_t beg = readlane(mb, k), end = readlane(me, k), ss = readlane(ms, k);
-      // B tile: the frontier words of the set's sigma columns
-      const uint32_t col = ss * SIG + lane;
-      const uint64_t bw = (lane < (uint32_t)SIG && col < p.n) ? p.front[col] : 0ull;
-      uint64_t B[SIG];
+    uint64_t pick = __ballot(mine);
+    // Two VSSs per step at sigma <= 16 (their B tiles, 2 x sigma 64-bit words, are
+    // broadcast to scalar registers): the B-tile and slice loads of both are issued
+    // before either is applied, and so are their visited-pair reads, which halves
+    // the chain of dependent round trips per VSS.  At sigma = 32 two tiles would not
+    // fit the scalar registers, so one VSS per step.
+    constexpr int P = SIG <= 16 ? 2 : 1;
+    while (pick) {
+      uint32_t beg[P], end[P], ss[P];
 #pragma unroll
-      for (int j = 0; j < SIG; ++j) B[j] = readlane64(bw, j);
-      MT m[SLOTS];
-      uint32_t u[SLOTS];
-#pragma unroll
-      for (int r = 0; r < SLOTS; ++r) {
-        const uint32_t idx = beg + lane + r * kWave;
-        const bool ok = idx < end;
-        m[r] = ok ? masks[idx] : MT(0);
-        u[r] = ok ? p.row_ids[idx] : 0u;
+      for (int h = 0; h < P; ++h) {
+        const bool any = pick != 0;
+        const uint32_t k = any ? __ffsll((unsigned long long)pick) - 1 : 0u;
+        if (any) pick &= pick - 1;
+        beg[h] = readlane(mb, k);
+        end[h] = any ? readlane(me, k) : beg[h];  // no VSS left: an empty one
+        ss[h] = readlane(ms, k);
       }
-      uint64_t acc[SLOTS];
-      ulonglong2 cv[SLOTS];
+      // B tiles: the frontier words of each set's sigma columns
+      uint64_t bw[P];
 #pragma unroll
-      for (int r = 0; r < SLOTS; ++r) {
-        uint64_t a = 0;
-#pragma unroll
-        for (int j = 0; j < SIG; ++j) a |= ((uint32_t)m[r] >> j & 1u) ? B[j] : 0ull;
-        acc[r] = a;
-        cv[r] = reinterpret_cast<const ulonglong2*>(p.vis)[a ? u[r] : 0u];
+      for (int h = 0; h < P; ++h) {
+        const uint32_t col = ss[h] * SIG + lane;
+        bw[h] = (lane < (uint32_t)SIG && col < p.n && end[h] > beg[h]) ? p.front[col] : 0ull;
       }
+      MT m[P][SLOTS];
+      uint32_t u[P][SLOTS];
 #pragma unroll
-      for (int r = 0; r < SLOTS; ++r) {
-        const uint64_t fresh = acc[r] & ~cv[r].x & ~cv[r].y;
-        if (fresh) {
-          atomicOr(p.vis + 2 * (uint64_t)u[r] + 1, (unsigned long long)fresh);
-          // Every level starts with next == current for all vertices, so the first
-          // OR that changes u's next word was issued by a thread that read them
-          // equal: only such threads need to mark u touched.
-          if (mark && cv[r].y == cv[r].x) p.touched[u[r]] = 1;
+      for (int h = 0; h < P; ++h)
+#pragma unroll
+        for (int r = 0; r < SLOTS; ++r) {
+          const uint32_t idx = beg[h] + lane + r * kWave;
+          const bool ok = idx < end[h];
+          m[h][r] = ok ? masks[idx] : MT(0);
+          u[h][r] = ok ? p.row_ids[idx] : 0u;
+        }
+      uint64_t acc[P][SLOTS];
+      ulonglong2 cv[P][SLOTS];
+#pragma unroll
+      for (int h = 0; h < P; ++h) {
+        uint64_t B[SIG];
+#pragma unroll
+        for (int j = 0; j < SIG; ++j) B[j] = readlane64(bw[h], j);
+#pragma unroll
+        for (int r = 0; r < SLOTS; ++r) {
+          uint64_t a = 0;
+#pragma unroll
+          for (int j = 0; j < SIG; ++j) a |= ((uint32_t)m[h][r] >> j & 1u) ? B[j] : 0ull;
+          acc[h][r] = a;
+          cv[h][r] = reinterpret_cast<const ulonglong2*>(p.vis)[a ? u[h][r] : 0u];
         }
       }
+#pragma unroll
+      for (int h = 0; h < P; ++h)
+#pragma unroll
+        for (int r = 0; r < SLOTS; ++r) {
+          const uint64_t fresh = acc[h][r] & ~cv[h][r].x & ~cv[h][r].y;
+          if (fresh) {
+            atomicOr(p.vis + 2 * (uint64_t)u[h][r] + 1, (unsigned long long)fresh);
+            // Every level starts with next == current for all vertices, so the first
+            // OR that changes u's next word was issued by a thread that read them
+            // equal: only such threads need to mark u touched.
+            if (mark && cv[h][r].y == cv[h][r].x) p.touched[u[h][r]] = 1;
+          }
+        }
     }
   }
 }
@@ -198,7 +242,7 @@ __device__ __forceinline__ void multi_stage2(const MultiParams& p, uint32_t* qn,
     }
     __syncthreads();
     const uint32_t pos = s_base + s_wave[wave] + incl - cnt;
-    wave_push<1>(qn, pos, cnt, vb, vn);
+    wave_push<1>(qn, pos, cnt, vb, vn, vb /* tags: unused */, MultiEntry{p.nranges > 1 ? p.vss_range : nullptr});
     __syncthreads();
   }
 }
@@ -231,7 +275,8 @@ __global__ __launch_bounds__(1024) void bfs_multi_persistent(MultiParams p) {
     uint32_t off = 0;
     for (uint32_t i = 0; i < p.n_init_sets; ++i) {
       const uint32_t b = p.real_ptrs[p.init_sets[i]], e = p.real_ptrs[p.init_sets[i] + 1];
-      for (uint32_t j = tid; j < e - b; j += nt) p.queue[off + j] = b + j;
+      for (uint32_t j = tid; j < e - b; j += nt)
+        p.queue[off + j] = MultiEntry{p.nranges > 1 ? p.vss_range : nullptr}(b + j, 0u);
       off += e - b;
     }
     if (tid == 0) {
@@ -285,6 +330,7 @@ hipError_t launch_bfs_multi(const MultiParams& p, uint32_t sigma, uint32_t slots
                             hipStream_t stream) {
   const void* k = bfs_multi_kernel_symbol(sigma, slots);
   if (!k) return hipErrorInvalidValue;
+  if (p.nranges == 0 || p.nranges > kMaxRanges || grid % p.nranges != 0) return hipErrorInvalidValue;
   MultiParams copy = p;
   void* args[] = {&copy};
   return hipLaunchCooperativeKernel(k, dim3(grid), dim3(block), args, 0, stream);

@@ -104,12 +104,15 @@ class Server:
         self.outstanding -= self.footprint(r.graph, r.k)
         r.released = True
 
-    def run(self, trace, realtime: bool = True, keep: bool = True, on_done=None, poll_sleep: float = 20e-6):
+    def run(self, trace, realtime: bool = True, keep: bool = True, on_done=None, poll_sleep: float = 20e-6,
+            progress=None, progress_s: float = 30.0):
         """Replays `trace` [(t_arrival, graph, sources)] and returns the requests.
         realtime=False makes every request arrive at t = 0 (a closed-loop stress
         test).  keep=False releases each request (and drops its output) right after
-        on_done(request) returns."""
+        on_done(request) returns.  progress(done, total), if given, is called about
+        every progress_s seconds."""
         t0 = time.perf_counter()
+        t_prog, n_done = t0, 0
         reqs = [Request(i, g, np.asarray(s, np.uint32), t0 + (t if realtime else 0.0)) for i, (t, g, s) in
                 enumerate(trace)]
         arrivals = collections.deque(reqs)
@@ -145,6 +148,7 @@ class Server:
                     continue
                 r = inflight.pop(t)
                 r.done_at = time.perf_counter()
+                n_done += 1
                 r.depth, r.admit_iter, r.done_iter = depth, a, d
                 progressed = True
                 if on_done is not None:
@@ -155,6 +159,9 @@ class Server:
             if keep and waiting and not inflight and not progressed and \
                     self.outstanding + self.footprint(waiting[0].graph, waiting[0].k) > self.budget:
                 raise RuntimeError("budget held by kept requests: release them or use keep=False")
+            if progress is not None and time.perf_counter() - t_prog > progress_s:
+                t_prog = time.perf_counter()
+                progress(n_done, len(reqs))
             if not progressed:
                 time.sleep(poll_sleep)
         return reqs

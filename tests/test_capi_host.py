@@ -246,7 +246,7 @@ def test_jaccard_windows_matches_oracle(seed):
         n = int(rng.integers(20, 300))
         m = n * int(rng.integers(1, 6))
         gr = inputs.from_arcs(n, rng.integers(0, n, m), rng.integers(0, n, m), bool(seed % 3))
-    g = host_graph(gr, sigma=sigma, window=w, reorder="compression")
+    g = host_graph(gr, sigma=sigma, window=w, reorder="compression", prepass="off")
     np.testing.assert_array_equal(g.export("order_id"), oreorder.jaccard_with_windows(gr, sigma, w))
     if not g.stats()["hubs_sorted"]:
         np.testing.assert_array_equal(g.export("new_id"), g.export("order_id"))
@@ -258,7 +258,7 @@ def test_jaccard_windows_matches_oracle_hand_cases():
         src = [u for u, vs in adj.items() for _ in vs]
         dst = [v for vs in adj.values() for v in vs]
         gr = inputs.from_arcs(n, src, dst, False)
-        g = host_graph(gr, sigma=sigma, window=w, reorder="compression", hubs="off")
+        g = host_graph(gr, sigma=sigma, window=w, reorder="compression", hubs="off", prepass="off")
         np.testing.assert_array_equal(g.export("new_id"), oreorder.jaccard_with_windows(gr, sigma, w))
 
 
@@ -420,3 +420,66 @@ def test_traffic_record_hash_scope():
     a = profsum.kernel_source_hash(profsum.SINGLE_SOURCE_FILES)
     assert a == profsum.kernel_source_hash(list(reversed(profsum.SINGLE_SOURCE_FILES)))
     assert a != profsum.kernel_source_hash(profsum.SINGLE_SOURCE_FILES[:-1])
+
+
+SHINGLE_SEED = 0x243F6A8885A308D3  # the library's default seed
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_shingle_prepass_matches_oracle(seed):
+    from oracle import prepass as oprepass
+    rng = np.random.default_rng(40 + seed)
+    k = [1, 2, 3, 8][seed]
+    if seed % 2 == 0:
+        gr = inputs.rmat_workload(8, 8, seed=seed, permute_seed=seed + 5)
+    else:
+        n = int(rng.integers(30, 200))
+        m = n * int(rng.integers(1, 5))
+        gr = inputs.from_arcs(n, rng.integers(0, n, m), rng.integers(0, n, m), bool(seed % 3))
+    hseed = SHINGLE_SEED if seed < 2 else int(rng.integers(1 << 62))
+    sigma, w = 8, 8 * int(rng.integers(2, 6))
+    g = host_graph(gr, sigma=sigma, window=w, reorder="compression", hubs="off", prepass="shingle", shingles=k,
+                   shingle_seed=hseed)
+    assert g.stats()["prepass_used"] == 1
+    np.testing.assert_array_equal(g.export("prepass_id"), oprepass.shingle_order(gr, k, hseed))
+    np.testing.assert_array_equal(g.export("order_id"), oprepass.prepass_then_windows(gr, k, hseed, sigma, w))
+
+
+def test_shingle_prepass_defaults_and_switches():
+    gr = inputs.rmat_workload(9, 8, seed=3, permute_seed=4)
+    auto = host_graph(gr, reorder="compression")
+    on = host_graph(gr, reorder="compression", prepass="shingle")
+    off = host_graph(gr, reorder="compression", prepass="off")
+    assert auto.stats()["prepass_used"] == 0 and on.stats()["prepass_used"] == 1 and off.stats()["prepass_used"] == 0
+    np.testing.assert_array_equal(auto.export("order_id"), off.export("order_id"))
+    # two min-hashes and the seed 0x243F6A8885A308D3 by default
+    from oracle import prepass as oprepass
+    np.testing.assert_array_equal(on.export("prepass_id"), oprepass.shingle_order(gr, 2, SHINGLE_SEED))
+    np.testing.assert_array_equal(off.export("prepass_id"), np.arange(gr.n))
+    np.testing.assert_array_equal(off.export("order_id"), oreorder.jaccard_with_windows(gr, 8, 1 << 16))
+    # RCM and the given labels never run the pre-pass
+    for r in ("bandwidth", "none"):
+        h = host_graph(gr, reorder=r, prepass="shingle")
+        assert h.stats()["prepass_used"] == 0
+        np.testing.assert_array_equal(h.export("prepass_id"), np.arange(gr.n))
+    with pytest.raises(blest.BlestError):
+        host_graph(gr, prepass="shingle", shingles=9)
+
+
+def test_shingle_prepass_groups_planted_twins():
+    """Twin groups scattered by a permutation end up one slice set each when the
+    pre-pass runs first; Algorithm 1 alone, with windows of one slice set, cannot
+    gather them (the oracle's pin of the same case)."""
+    sigma, groups, fan = 8, 64, 6
+    src, dst = [], []
+    for gi in range(groups):
+        for j in range(sigma):
+            for t in range(fan):
+                src.append(gi * sigma + j)
+                dst.append(groups * sigma + gi * fan + t)
+    n = groups * (sigma + fan)
+    gr = inputs.relabel(inputs.from_arcs(n, src, dst, False), inputs.permutation(n, 9))
+    on = host_graph(gr, reorder="compression", window=sigma, prepass="shingle", hubs="off")
+    off = host_graph(gr, reorder="compression", window=sigma, prepass="off", hubs="off")
+    assert on.stats()["num_slices"] == groups * fan
+    assert off.stats()["num_slices"] > groups * fan

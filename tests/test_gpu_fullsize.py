@@ -58,14 +58,18 @@ def test_s22_all_64_sources(s22):
 
 
 def test_s20_k64_all_rows():
+    """Every row, with the k-source kernel on the base VSS partition and on its own
+    partition cut at 8 row ranges."""
     gr = inputs.rmat_workload(20, 16, seed=1)
-    g = blest.Graph(gr, reorder="none")
     srcs = inputs.sources(gr, seed=7, k=64, distinct=True)
-    say(f"S20 x 64: n={gr.n} arcs={gr.nnz}")
-    got = g.bfs_multi(srcs).cpu().numpy()
     want = oracle_pool.rows(gr, srcs)
-    for j in range(64):
-        np.testing.assert_array_equal(got[j], want[j], err_msg=f"S20 row {j} source {int(srcs[j])}")
+    for ranges in (1, 8):
+        g = blest.Graph(gr, reorder="none", multi_ranges=ranges)
+        say(f"S20 x 64: n={gr.n} arcs={gr.nnz} ranges {ranges}")
+        got = g.bfs_multi(srcs).cpu().numpy()
+        for j in range(64):
+            np.testing.assert_array_equal(got[j], want[j], err_msg=f"S20 ranges {ranges} row {j} source {int(srcs[j])}")
+        g.close()
 
 
 def test_grid4096_all_16_sources():

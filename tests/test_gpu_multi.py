@@ -154,3 +154,22 @@ def test_levels_switch_between_dense_and_sparse():
     for reorder in ("none", "compression"):
         g = blest.Graph(gr, reorder=reorder)
         np.testing.assert_array_equal(run_multi(g, srcs), oracle.bfs_multi(gr, srcs), err_msg=reorder)
+
+
+@pytest.mark.parametrize("ranges", [2, 8, 32])
+def test_row_range_partition(ranges):
+    """The k-source kernel's own VSS partition cut at row ranges, each workgroup
+    pulling one range: R-MAT (dense and sparse levels) and a grid, 64 sources."""
+    gr = inputs.rmat_workload(14, 16, seed=ranges, permute_seed=2)
+    g = blest.Graph(gr, reorder="none", multi_ranges=ranges)
+    st = g.stats()
+    assert st["multi_ranges"] == ranges and st["multi_num_vss"] >= st["num_vss"]
+    srcs = inputs.sources(gr, seed=5, k=64, distinct=True)
+    np.testing.assert_array_equal(run_multi(g, srcs), oracle.bfs_multi(gr, srcs))
+    grid = inputs.grid_workload(80, 0.9, seed=ranges, permute_seed=3)
+    g = blest.Graph(grid, reorder="bandwidth", multi_ranges=ranges)
+    srcs = inputs.sources(grid, seed=6, k=33)
+    np.testing.assert_array_equal(run_multi(g, srcs), oracle.bfs_multi(grid, srcs))
+    # the single-source kernel keeps its own partition
+    s = int(srcs[0])
+    np.testing.assert_array_equal(g.bfs(s).cpu().numpy(), oracle.bfs(grid, s))
