@@ -200,6 +200,9 @@ def run_single(args):
         opts.update(tuned)
     if args.window:
         opts["window"] = args.window
+    for k in ("block", "blocks_per_cu", "lds_kib"):
+        if getattr(args, k):
+            opts[k] = getattr(args, k)
     g = blest.Graph(gr, device=0, ranges=args.ranges, prepass=args.prepass, **opts)
     st = g.stats()
     if tuned:
@@ -418,8 +421,9 @@ def run_wsweep(args):
     permuted = inputs.rmat_workload(22, 16, seed=1, permute_seed=2)
     natural = inputs.rmat_workload(22, 16, seed=1)
     sources = inputs.sources(permuted, seed=3, k=64)
-    runs = [("permuted", "none", 1 << 16), ("generator", "none", 1 << 16)] + \
-           [("permuted", "compression", 1 << e) for e in (3, 6, 9, 12, 14, 16, 18)]
+    runs = [("permuted", "none", 1 << 16, "off"), ("generator", "none", 1 << 16, "off")] + \
+           [("permuted", "compression", 1 << e, "off") for e in (3, 6, 9, 12, 14, 16, 18)] + \
+           [("permuted", "compression", 1 << e, "shingle") for e in args.prepass_windows]
     stream = torch.cuda.current_stream()
     out = torch.empty(permuted.n, dtype=torch.int32, device="cuda")
     # generator vertex v is permuted vertex perm[v]: map the sources back
@@ -428,11 +432,11 @@ def run_wsweep(args):
     inv[perm] = np.arange(permuted.n, dtype=np.uint32)
     degs = {"permuted": permuted.degrees(), "generator": natural.degrees()}
     sweep, headline, total_ms = [], None, 0.0
-    for labels, reorder, w in runs:
+    for labels, reorder, w, prepass in runs:
         gr = permuted if labels == "permuted" else natural
         src = sources if labels == "permuted" else inv[sources]
         t0 = time.time()
-        g = blest.Graph(gr, reorder=reorder, window=w, update="lazy", device=0)
+        g = blest.Graph(gr, reorder=reorder, window=w, update="lazy", prepass=prepass, device=0)
         st = g.stats()
         build_s = time.time() - t0
         edges = 0.0
@@ -448,6 +452,7 @@ def run_wsweep(args):
         wall = time.perf_counter() - t1
         g.close()
         rec = {"labels": labels, "reorder": reorder, "window": w if reorder == "compression" else None,
+               "prepass": "shingle" if st["prepass_used"] else None,
                "compression": round(st["compression"], 4), "num_vss": st["num_vss"],
                "reorder_s": round(st["reorder_seconds"], 2), "build_s": round(build_s, 2),
                "ms_per_bfs": round(wall * 1000 / (args.steps * len(src)), 4),
@@ -455,10 +460,11 @@ def run_wsweep(args):
         log(f"[bench] {rec}")
         sweep.append(rec)
         total_ms += wall * 1000 / args.steps
-        if labels == "permuted" and reorder == "compression" and w == 1 << 16:
+        if labels == "permuted" and reorder == "compression" and w == 1 << 16 and prepass == "off":
             headline = rec
-    config = {"workload": "R-MAT scale 22 ef 16, 64 sources, lazy; Algorithm 1 window sweep w = 2^3..2^18 "
-                          "and no reordering (permuted and generator labels); value at w = 65536",
+    config = {"workload": "R-MAT scale 22 ef 16, 64 sources, lazy; Algorithm 1 window sweep w = 2^3..2^18, "
+                          "with the shingle pre-pass at the listed windows, and no reordering (permuted and "
+                          "generator labels); value at w = 65536 without the pre-pass",
               "n": permuted.n, "arcs": int(permuted.nnz), "sources": len(sources)}
     line(headline["gteps"], args, total_ms / len(runs), "u32", config, None, None, {"sweep": sweep})
 
@@ -698,11 +704,14 @@ def serve_sweep(handles, graphs, rhos, nreq, budget, log_prefix="[bench]"):
     edges_of = lambda r: float(sum(comp[r.graph][1][comp[r.graph][0][int(s)]] for s in r.sources))
     src_of = lambda g, seed, k: inputs.sources(graphs[g], seed=seed, k=k)
     srv = Server(handles, budget)
-    lone = []
+    lone, lone_graph = [], []
     for t, gname, s in poisson_trace(99, 1.0, 40, names, src_of):
         lone.append(srv.run([(0.0, gname, s)], realtime=False, keep=False)[0].latency)
+        lone_graph.append(gname)
     service = float(np.mean(lone[8:]))
-    log(f"{log_prefix} mean lone service time {service * 1000:.2f} ms")
+    lone_by_graph = {g: round(float(np.mean([x for x, h in zip(lone[8:], lone_graph[8:]) if h == g])) * 1000, 3)
+                     for g in names if g in lone_graph[8:]}
+    log(f"{log_prefix} mean lone service time {service * 1000:.2f} ms; by graph (ms): {lone_by_graph}")
     sweep = []
     for rho in rhos:
         trace = poisson_trace(int(rho * 1000) + 17, rho / service, nreq, names, src_of)
@@ -710,7 +719,7 @@ def serve_sweep(handles, graphs, rhos, nreq, budget, log_prefix="[bench]"):
                        progress=lambda d, n, rho=rho: log(f"{log_prefix} rho {rho}: {d}/{n} requests done"))
         s = summarize(reqs, edges_of)
         wait = np.array([r.submitted_at - r.arrival for r in reqs]) * 1000.0
-        s.update({"rho": rho, "rate_per_s": round(rho / service, 2), "p50_host_wait_ms": float(np.percentile(wait, 50)),
+        s.update({"rho": rho, "rate_per_s": round(rho / service, 2), "lone_ms_by_graph": lone_by_graph, "p50_host_wait_ms": float(np.percentile(wait, 50)),
                   "p99_host_wait_ms": float(np.percentile(wait, 99)),
                   "budget_waits": int(np.sum(wait > 1.0)), "rejected": 0,
                   "overlapping_pairs": overlapping_pairs(reqs), "peak_output_bytes": srv.peak_bytes,
@@ -795,6 +804,11 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg of the default workload")
     ap.add_argument("--serve-leg-requests", type=int, default=400)
     ap.add_argument("--no-tuned", action="store_true", help="ignore the autotuner's stored choices")
+    ap.add_argument("--prepass-windows", default="10,12,16", type=lambda x: [int(e) for e in x.split(",") if e],
+                    help="log2 windows of the wsweep entries with the shingle pre-pass")
+    ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: the library default)")
+    ap.add_argument("--blocks-per-cu", type=int, default=0, help="workgroups per CU (0: the library default)")
+    ap.add_argument("--lds-kib", type=int, default=0, help="LDS visited cache per workgroup (0: auto)")
     ap.add_argument("--window", type=int, default=0, help="Algorithm 1 window (0: the library default)")
     ap.add_argument("--prepass", default="auto", choices=["auto", "off", "shingle"],
                     help="locality pre-pass before Algorithm 1 (single-source workloads)")

@@ -72,7 +72,8 @@ enum { BLEST_UPDATE_AUTO = 0, BLEST_UPDATE_EAGER = 1, BLEST_UPDATE_LAZY = 2, BLE
 typedef struct {
   uint32_t sigma;      /* slice width in columns: 8 (the paper's value), 16 or 32 */
   uint32_t slots;      /* slices per lane of a 64-lane wavefront: tau = 64 * slots (1, 2, 4, 8; default 2) */
-  uint32_t window;     /* Algorithm 1 window w, a multiple of sigma (default 65536) */
+  uint32_t window;     /* Algorithm 1 window w, a multiple of sigma; 0 = auto (the default): 65536, or
+                          4096 after the shingle pre-pass */
   int32_t reorder;     /* BLEST_REORDER_* */
   int32_t update;      /* BLEST_UPDATE_* */
   int32_t device;      /* HIP device ordinal; -1 builds host-only (structure and stats) */
@@ -102,8 +103,8 @@ typedef struct {
                           workgroup b pulls range b % R only, so that each XCD's L2 holds one
                           range's visited pairs */
   uint32_t prepass;    /* locality pre-pass before Algorithm 1 (Section 2.2 runs Gorder there): 0 = auto
-                          (off), 1 = off, 2 = shingle ordering (vertices sorted by min-hashes of their
-                          out-neighbour sets, Chierichetti et al., KDD 2009) */
+                          (on whenever Algorithm 1 runs), 1 = off, 2 = shingle ordering (vertices sorted
+                          by min-hashes of their out-neighbour sets, Chierichetti et al., KDD 2009) */
   uint32_t shingles;   /* min-hashes per vertex of the shingle ordering, 1..8 (0 = 2) */
   uint64_t shingle_seed; /* seed of its hash functions: h_i(u) is output u + 1 of the SplitMix64 stream
                           (Steele, Lea and Flood, OOPSLA 2014) seeded with output i + 1 of the stream
@@ -147,6 +148,7 @@ typedef struct {
   uint32_t multi_num_vss;       /* VSSs of that partition */
   int32_t prepass_used;         /* 1 if the shingle pre-pass ran before Algorithm 1 */
   double prepass_seconds;       /* its host time (included in reorder_seconds) */
+  uint32_t window_used;         /* Algorithm 1 window applied (0: Algorithm 1 did not run) */
 } blest_stats_t;
 
 /* Fills *opt with the defaults listed above. */

@@ -75,7 +75,7 @@ class Stats(ctypes.Structure):
                 ("blocks_per_cu_runtime", ctypes.c_uint32), ("blocks_per_cu_own", ctypes.c_uint32),
                 ("eager_max", ctypes.c_uint32), ("packed", ctypes.c_int32), ("multi_ranges", ctypes.c_uint32),
                 ("multi_num_vss", ctypes.c_uint32), ("prepass_used", ctypes.c_int32),
-                ("prepass_seconds", ctypes.c_double)]
+                ("prepass_seconds", ctypes.c_double), ("window_used", ctypes.c_uint32)]
 
 
 _lib = None
@@ -191,7 +191,7 @@ class Graph:
     listing out-neighbours.  device=-1 builds the host structure only (statistics
     and exports work; BFS calls raise)."""
 
-    def __init__(self, csr, *, sigma=8, slots=2, window=1 << 16, reorder="auto", update="auto",
+    def __init__(self, csr, *, sigma=8, slots=2, window=0, reorder="auto", update="auto",
                  device=0, threads=0, block=0, blocks_per_cu=0, group=0, ranges=0, hubs="auto", lds_kib=0,
                  eager_max=0, pack=True, multi_ranges=0, prepass="auto", shingles=0, shingle_seed=None):
         o = default_options()

@@ -104,7 +104,7 @@ def _round(g, sources, k, stream):
     return [g.bfs_multi(np.asarray(sources, np.uint32), stream=stream)]
 
 
-def autotune(csr, sources, *, k=1, cands=None, repeats=3, reorder="auto", window=1 << 16, device=0, log=None):
+def autotune(csr, sources, *, k=1, cands=None, repeats=3, reorder="auto", window=0, device=0, log=None):
     """Times every candidate on `sources` and returns (best Trial, [Trial...]).
 
     k = 1 times one single-source BFS per source; k > 1 times one k-source call on

@@ -66,6 +66,13 @@ DeviceSerial g_serial[64];
 // check visited bits in memory only: refilling the LDS cache costs about as much
 // as such a level's checks.
 constexpr uint32_t kLdsMinQueue = 4096;
+// Default Algorithm 1 windows.  After the shingle pre-pass, vertices with shared
+// neighbours are already close, and a small window keeps nearly all of the
+// compression (R-MAT scale 22: 0.1400 at 4096 against 0.1416 at 65536) at a
+// fraction of the ordering time, which grows with the window once the candidate
+// lists of a window are dense.
+constexpr uint32_t kWindowAlone = 1u << 16;
+constexpr uint32_t kWindowAfterPrepass = 1u << 12;
 
 }  // namespace
 
@@ -81,6 +88,7 @@ struct blest_graph {
   std::vector<uint32_t> order_id; // original -> label after the ordering alone (before the hub sort)
   std::vector<uint32_t> prepass_id; // original -> label after the shingle pre-pass alone (empty: none)
   int prepass_used = 0;
+  uint32_t window_used = 0;  // Algorithm 1 window (0: Algorithm 1 did not run)
   double prepass_seconds = 0;
   std::vector<uint32_t> orig_id;  // new -> original
   bool identity = true;
@@ -175,7 +183,7 @@ blest_status map_rc(int rc) {
 bool valid_options(const blest_options& o) {
   if (o.sigma != 8 && o.sigma != 16 && o.sigma != 32) return false;
   if (o.slots != 1 && o.slots != 2 && o.slots != 4 && o.slots != 8) return false;
-  if (o.window == 0 || o.window % o.sigma != 0) return false;
+  if (o.window % o.sigma != 0) return false;  // 0 = auto
   if (o.reorder < BLEST_REORDER_AUTO || o.reorder > BLEST_REORDER_BANDWIDTH) return false;
   if (o.update < BLEST_UPDATE_AUTO || o.update > BLEST_UPDATE_ADAPTIVE) return false;
   if (o.block % 64 != 0 || o.block > 1024) return false;
@@ -476,7 +484,7 @@ void blest_default_options(blest_options* o) {
   if (!o) return;
   o->sigma = 8;
   o->slots = 2;
-  o->window = 1u << 16;
+  o->window = 0;
   o->reorder = BLEST_REORDER_AUTO;
   o->update = BLEST_UPDATE_AUTO;
   o->device = 0;
@@ -531,7 +539,10 @@ blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, cons
     } else {
       Csr gt;
       transpose(csr, gt);
-      if (reorder == BLEST_REORDER_COMPRESSION && o.prepass == 2) {
+      const bool prepass = reorder == BLEST_REORDER_COMPRESSION && o.prepass != 1;
+      if (reorder == BLEST_REORDER_COMPRESSION)
+        g->window_used = o.window ? o.window : prepass ? kWindowAfterPrepass : kWindowAlone;
+      if (prepass) {
         // shingle pre-pass, then Algorithm 1's windows over the pre-pass labels
         const double tp = now_s();
         shingle_order(csr, o.shingles ? o.shingles : 2, o.shingle_seed, T, g->prepass_id);
@@ -541,11 +552,11 @@ blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, cons
         g->prepass_used = 1;
         g->prepass_seconds = now_s() - tp;
         std::vector<uint32_t> win_id;
-        jaccard_windows(pre, pret, o.sigma, o.window, T, win_id);
+        jaccard_windows(pre, pret, o.sigma, g->window_used, T, win_id);
         g->new_id.resize(n);
         for (uint32_t v = 0; v < n; ++v) g->new_id[v] = win_id[g->prepass_id[v]];
       } else if (reorder == BLEST_REORDER_COMPRESSION) {
-        jaccard_windows(csr, gt, o.sigma, o.window, T, g->new_id);
+        jaccard_windows(csr, gt, o.sigma, g->window_used, T, g->new_id);
       } else {
         Csr und;
         undirected(csr, gt, und);
@@ -914,6 +925,7 @@ blest_status blest_stats(blest_handle h, blest_stats_t* o) {
   o->reorder_seconds = h->reorder_seconds;
   o->prepass_used = h->prepass_used;
   o->prepass_seconds = h->prepass_seconds;
+  o->window_used = h->window_used;
   o->build_seconds = h->build_seconds;
   o->hubs_sorted = h->hubs_sorted;
   o->grid = h->grid;

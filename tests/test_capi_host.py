@@ -450,17 +450,22 @@ def test_shingle_prepass_defaults_and_switches():
     auto = host_graph(gr, reorder="compression")
     on = host_graph(gr, reorder="compression", prepass="shingle")
     off = host_graph(gr, reorder="compression", prepass="off")
-    assert auto.stats()["prepass_used"] == 0 and on.stats()["prepass_used"] == 1 and off.stats()["prepass_used"] == 0
-    np.testing.assert_array_equal(auto.export("order_id"), off.export("order_id"))
+    assert auto.stats()["prepass_used"] == 1 and on.stats()["prepass_used"] == 1 and off.stats()["prepass_used"] == 0
+    # default windows: 4096 after the pre-pass, 65536 without it
+    assert auto.stats()["window_used"] == 4096 and off.stats()["window_used"] == 65536
+    np.testing.assert_array_equal(auto.export("order_id"), on.export("order_id"))
     # two min-hashes and the seed 0x243F6A8885A308D3 by default
     from oracle import prepass as oprepass
     np.testing.assert_array_equal(on.export("prepass_id"), oprepass.shingle_order(gr, 2, SHINGLE_SEED))
+    np.testing.assert_array_equal(on.export("order_id"), oprepass.prepass_then_windows(gr, 2, SHINGLE_SEED, 8, 4096))
+    explicit = host_graph(gr, reorder="compression", window=64)
+    assert explicit.stats()["window_used"] == 64
     np.testing.assert_array_equal(off.export("prepass_id"), np.arange(gr.n))
     np.testing.assert_array_equal(off.export("order_id"), oreorder.jaccard_with_windows(gr, 8, 1 << 16))
     # RCM and the given labels never run the pre-pass
     for r in ("bandwidth", "none"):
         h = host_graph(gr, reorder=r, prepass="shingle")
-        assert h.stats()["prepass_used"] == 0
+        assert h.stats()["prepass_used"] == 0 and h.stats()["window_used"] == 0
         np.testing.assert_array_equal(h.export("prepass_id"), np.arange(gr.n))
     with pytest.raises(blest.BlestError):
         host_graph(gr, prepass="shingle", shingles=9)

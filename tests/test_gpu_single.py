@@ -203,8 +203,22 @@ def test_full_size_s22_config_sampled_sources():
     g = blest.Graph(gr, reorder="compression")
     st = g.stats()
     assert st["update_used"] == "lazy" and st["nranges"] == 1 and st["hubs_sorted"] == 1
+    assert st["prepass_used"] == 1 and st["window_used"] == 4096
     assert st["lds_bytes"] == 128 * 1024 and st["lds_bytes"] * 8 < gr.n
     check_sources(gr, g, inputs.sources(gr, seed=3, k=64)[:2])
+
+
+@pytest.mark.parametrize("prepass,window", [("shingle", 0), ("shingle", 1 << 16), ("off", 0)])
+def test_shingle_prepass_orderings(prepass, window):
+    """The shingle pre-pass before Algorithm 1 (default window and a large one) and
+    Algorithm 1 alone: every ordering is a relabelling, so levels in the caller's
+    IDs must match the oracle on every source."""
+    gr = inputs.rmat_workload(14, 16, seed=21, permute_seed=22)
+    g = blest.Graph(gr, reorder="compression", prepass=prepass, window=window)
+    st = g.stats()
+    assert st["prepass_used"] == (prepass == "shingle")
+    assert st["window_used"] == (window or (4096 if prepass == "shingle" else 65536))
+    check_sources(gr, g, inputs.sources(gr, seed=23, k=6))
 
 
 def _csr_arcs(gr, offset):
