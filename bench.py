@@ -704,14 +704,19 @@ def serve_sweep(handles, graphs, rhos, nreq, budget, log_prefix="[bench]"):
     edges_of = lambda r: float(sum(comp[r.graph][1][comp[r.graph][0][int(s)]] for s in r.sources))
     src_of = lambda g, seed, k: inputs.sources(graphs[g], seed=seed, k=k)
     srv = Server(handles, budget)
-    lone, lone_graph = [], []
+    lone, lone_graph, lone_iters = [], [], []
     for t, gname, s in poisson_trace(99, 1.0, 40, names, src_of):
-        lone.append(srv.run([(0.0, gname, s)], realtime=False, keep=False)[0].latency)
+        r = srv.run([(0.0, gname, s)], realtime=False, keep=False)[0]
+        lone.append(r.latency)
         lone_graph.append(gname)
+        lone_iters.append(max(r.done_iter - r.admit_iter, 1))
     service = float(np.mean(lone[8:]))
-    lone_by_graph = {g: round(float(np.mean([x for x, h in zip(lone[8:], lone_graph[8:]) if h == g])) * 1000, 3)
-                     for g in names if g in lone_graph[8:]}
-    log(f"{log_prefix} mean lone service time {service * 1000:.2f} ms; by graph (ms): {lone_by_graph}")
+    warm = list(zip(lone[8:], lone_graph[8:], lone_iters[8:]))
+    lone_by_graph = {g: {"ms": round(float(np.mean([x for x, h, _ in warm if h == g])) * 1000, 3),
+                         "iterations": round(float(np.mean([i for _, h, i in warm if h == g])), 1),
+                         "us_per_iteration": round(float(np.mean([x / i for x, h, i in warm if h == g])) * 1e6, 2)}
+                     for g in names if any(h == g for _, h, _ in warm)}
+    log(f"{log_prefix} mean lone service time {service * 1000:.2f} ms; by graph: {lone_by_graph}")
     sweep = []
     for rho in rhos:
         trace = poisson_trace(int(rho * 1000) + 17, rho / service, nreq, names, src_of)
