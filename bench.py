@@ -692,7 +692,7 @@ def component_edges(gr):
     return lab, np.bincount(lab, weights=gr.degrees().astype(np.float64)) / 2.0
 
 
-def serve_sweep(handles, graphs, rhos, nreq, budget, log_prefix="[bench]"):
+def serve_sweep(handles, graphs, rhos, nreq, budget, log_prefix="[bench]", seed_offset=0, dump=None):
     """Lone service time (closed loop, one request at a time), then one Poisson trace
     of `nreq` requests per offered load rho = rate * lone service time."""
     import numpy as np
@@ -719,10 +719,15 @@ def serve_sweep(handles, graphs, rhos, nreq, budget, log_prefix="[bench]"):
     log(f"{log_prefix} mean lone service time {service * 1000:.2f} ms; by graph: {lone_by_graph}")
     sweep = []
     for rho in rhos:
-        trace = poisson_trace(int(rho * 1000) + 17, rho / service, nreq, names, src_of)
+        trace = poisson_trace(int(rho * 1000) + 17 + seed_offset, rho / service, nreq, names, src_of)
         reqs = srv.run(trace, keep=False,
                        progress=lambda d, n, rho=rho: log(f"{log_prefix} rho {rho}: {d}/{n} requests done"))
         s = summarize(reqs, edges_of)
+        if dump:
+            np.savez(f"{dump}_rho{rho}_seed{seed_offset}.npz", latency=np.array([r.latency for r in reqs]),
+                     graph=np.array([names.index(r.graph) for r in reqs]), k=np.array([r.k for r in reqs]),
+                     edges=np.array([edges_of(r) for r in reqs]), arrival=np.array([r.arrival for r in reqs]),
+                     done=np.array([r.done_at for r in reqs]), rate=rho / service, service=service)
         wait = np.array([r.submitted_at - r.arrival for r in reqs]) * 1000.0
         s.update({"rho": rho, "rate_per_s": round(rho / service, 2), "lone_ms_by_graph": lone_by_graph, "p50_host_wait_ms": float(np.percentile(wait, 50)),
                   "p99_host_wait_ms": float(np.percentile(wait, 99)),
@@ -760,11 +765,13 @@ def run_serve(args):
         ", ".join(f"{k} {h.stats()['reorder_used']}/{h.stats()['update_used']}" for k, h in handles.items()))
     budget = 16 << 30
     rhos = tuple(float(x) for x in args.serve_rhos.split(",")) if args.serve_rhos else SERVE_RHOS
-    service, sweep, st = serve_sweep(handles, graphs, rhos, args.serve_requests, budget)
+    service, sweep, st = serve_sweep(handles, graphs, rhos, args.serve_requests, budget,
+                                     seed_offset=args.serve_seed, dump=args.serve_dump)
     best = max(s["gteps"] for s in sweep)
     config = {"workload": "Poisson requests (k=1 w.p. 1/2 else U{1..64}) over resident R-MAT S18, R-MAT S22, "
                           "grid 2048^2 p=0.9, continuous batching in one persistent server launch; HBM budget "
                           "16 GiB for outputs", "requests_per_rate": args.serve_requests,
+              "trace_seed_offset": args.serve_seed,
               "lone_service_ms": round(service * 1000, 3), "server_launches": st["launches"],
               "server_resident_bytes": st["resident_bytes"]}
     extra = {"serving": sweep}
@@ -808,6 +815,8 @@ def main():
     ap.add_argument("--serve-rhos", default="", help="comma-separated offered loads (default: the full sweep)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg of the default workload")
     ap.add_argument("--serve-leg-requests", type=int, default=400)
+    ap.add_argument("--serve-seed", type=int, default=0, help="offset of the serving traces' seeds")
+    ap.add_argument("--serve-dump", default="", help="write each rate's per-request records to PATH_rho*.npz")
     ap.add_argument("--no-tuned", action="store_true", help="ignore the autotuner's stored choices")
     ap.add_argument("--prepass-windows", default="10,12,16", type=lambda x: [int(e) for e in x.split(",") if e],
                     help="log2 windows of the wsweep entries with the shingle pre-pass")

@@ -37,9 +37,16 @@ namespace blest {
 namespace {
 
 constexpr uint64_t kDenseFrac = 16;  // dense Stage 2 when the queue holds >= 1/16 of the VSSs
+constexpr uint32_t kStage2Rounds = 4;  // words per thread and pass of Stage 2
 
 __device__ __forceinline__ uint32_t sys_load(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+// A poll of a host-written word: a relaxed system-scope load reads memory without
+// the cache invalidation an acquire at system scope costs; the control step issues
+// one acquire fence only when a poll shows new tickets.
+__device__ __forceinline__ uint32_t sys_poll(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ void sys_store(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -79,16 +86,33 @@ __device__ void serve_control(const ServeParams& p, uint32_t it) {
   // 1. finished columns (no new bit in the last iteration); per request slot, the
   // running-column count and the deepest level are kept by lane 0
   uint64_t done_slots[kServeRing / 64] = {};
+  // Every word this step reads from the state in the common case, loaded at once
+  // (a chain of dependent loads costs a memory round trip each): lane 4j + g holds
+  // active, admitted and alive of graph g for j = 0, 1, 2; lanes 12 and 13 the
+  // ticket counters; and every lane its column's admission iteration per graph.
+  // Only this wavefront writes active, admitted and the counters, and Stage 2's
+  // ORs into alive are complete (they precede the grid barrier before this step).
+  uint64_t wv = 0;
+  if (lane < 12 && (lane & 3u) < p.ngraphs)
+    wv = lane < 4 ? st->active[lane] : lane < 8 ? st->admitted[lane - 4] : st->alive[lane - 8];
+  const uint32_t cw = lane == 12 ? st->seen : lane == 13 ? st->consumed : 0u;
+  uint32_t cstart[kServeMaxGraphs];
+#pragma unroll
+  for (uint32_t g = 0; g < kServeMaxGraphs; ++g) cstart[g] = g < p.ngraphs ? st->col_start[g][lane] : 0u;
+  uint64_t actv[kServeMaxGraphs];  // active columns per graph, kept current below
+#pragma unroll
+  for (uint32_t g = 0; g < kServeMaxGraphs; ++g) actv[g] = readlane64(wv, g);
   for (uint32_t g = 0; g < p.ngraphs; ++g) {
-    const uint64_t act = u64_of_lane0(&st->active[g]);
+    const uint64_t act = actv[g];
     // a BFS has at most n + 1 levels: a column older than that is ended (a guard;
     // it never fires when Stage 2 reports growth correctly)
     const uint32_t n = g == 0 ? p.g[0].n : g == 1 ? p.g[1].n : g == 2 ? p.g[2].n : p.g[3].n;
-    const bool overdue = ((act >> lane) & 1ull) && it - st->col_start[g][lane] > n + 2;
+    const uint32_t cs = g == 0 ? cstart[0] : g == 1 ? cstart[1] : g == 2 ? cstart[2] : cstart[3];
+    const bool overdue = ((act >> lane) & 1ull) && it - cs > n + 2;
     // columns admitted by the previous control step start in this iteration: they
     // have not had a Stage 2 yet
-    const uint64_t fresh = u64_of_lane0(&st->admitted[g]);
-    const uint64_t fin = act & ((~u64_of_lane0(&st->alive[g]) & ~fresh) | __ballot(overdue));
+    const uint64_t fresh = readlane64(wv, 4 + g);
+    const uint64_t fin = act & ((~readlane64(wv, 8 + g) & ~fresh) | __ballot(overdue));
     if (!fin) continue;
     const bool mine = (fin >> lane) & 1ull;
     const uint32_t r = mine ? st->col_ticket[g][lane] % kServeRing : 0u;
@@ -107,8 +131,9 @@ __device__ void serve_control(const ServeParams& p, uint32_t it) {
       }
       left &= ~grp;
     }
+    actv[g] = act & ~fin;
     if (lane == 0) {
-      st->active[g] &= ~fin;
+      st->active[g] = actv[g];
       st->dirty[g] |= fin;
     }
   }
@@ -142,13 +167,18 @@ __device__ void serve_control(const ServeParams& p, uint32_t it) {
   // from the host) ends the launch at once, running columns or not.
   uint32_t n_admit = 0, exit_now = 0;
   const uint64_t t_idle0 = __builtin_amdgcn_s_memrealtime();
+  uint32_t seen = readlane(cw, 12), consumed = readlane(cw, 13);
   for (;;) {
-    if (readlane(sys_load(&mb->stop), 0) == 2) {
+    // both polls are issued before either is used
+    const uint32_t stop_w = sys_poll(&mb->stop), sub_w = sys_poll(&mb->submitted);
+    if (readlane(stop_w, 0) == 2) {
       exit_now = 1;
       break;
     }
-    const uint32_t sub = readlane(sys_load(&mb->submitted), 0);
-    uint32_t seen = u32_of_lane0(&st->seen);
+    const uint32_t sub = readlane(sub_w, 0);
+    // the host publishes a slot before it raises `submitted`: order the slot reads
+    // after the poll that saw it
+    if (sub != seen) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
     for (uint32_t c = 0; c < 16 && seen != sub; ++c, ++seen) {
       const uint32_t r = seen % kServeRing;
       const uint32_t* src = reinterpret_cast<const uint32_t*>(&mb->slot[r]);
@@ -163,14 +193,13 @@ __device__ void serve_control(const ServeParams& p, uint32_t it) {
     // admission, oldest first; a graph whose oldest waiting request does not fit
     // admits nothing newer this time (per-graph first-come order)
     uint32_t blocked = 0;
-    uint32_t consumed = u32_of_lane0(&st->consumed);
     for (uint32_t t = consumed; t != seen; ++t) {
       const uint32_t r = t % kServeRing;
       ServeSlot* ds = &st->slot[r];
       if (u32_of_lane0(&ds->state) != 1) continue;
       const uint32_t g = u32_of_lane0(&ds->graph), k = u32_of_lane0(&ds->k);
       if (g >= p.ngraphs || k == 0 || k > kServeCols || ((blocked >> g) & 1u)) continue;
-      const uint64_t freec = ~u64_of_lane0(&st->active[g]);
+      const uint64_t freec = ~(g == 0 ? actv[0] : g == 1 ? actv[1] : g == 2 ? actv[2] : actv[3]);
       if ((uint32_t)__popcll(freec) < k) {
         blocked |= 1u << g;
         continue;
@@ -188,6 +217,9 @@ __device__ void serve_control(const ServeParams& p, uint32_t it) {
         st->adm_src[n_admit + rank] = ds->src[rank];
       }
       n_admit += k;
+#pragma unroll
+      for (uint32_t h = 0; h < kServeMaxGraphs; ++h)
+        if (h == g) actv[h] |= taken;
       if (lane == 0) {
         st->active[g] |= taken;
         st->admitted[g] |= taken;
@@ -204,11 +236,13 @@ __device__ void serve_control(const ServeParams& p, uint32_t it) {
     while (consumed != seen && u32_of_lane0(&st->slot[consumed % kServeRing].state) >= 2) ++consumed;
     if (lane == 0) st->consumed = consumed;
     uint64_t any_active = 0;
-    for (uint32_t g = 0; g < p.ngraphs; ++g) any_active |= u64_of_lane0(&st->active[g]);
+#pragma unroll
+    for (uint32_t g = 0; g < kServeMaxGraphs; ++g) any_active |= actv[g];
     if (any_active || n_admit) break;
     // idle: nothing runs and nothing admissible waits
-    const uint32_t stop = readlane(sys_load(&mb->stop), 0);
-    const uint32_t sub2 = readlane(sys_load(&mb->submitted), 0);
+    const uint32_t stop_i = sys_poll(&mb->stop), sub_i = sys_poll(&mb->submitted);
+    const uint32_t stop = readlane(stop_i, 0);
+    const uint32_t sub2 = readlane(sub_i, 0);
     if (stop == 2 || (stop && consumed == seen && seen == sub2)) {
       exit_now = 1;
       break;
@@ -391,61 +425,81 @@ __device__ void serve_stage2(const ServeParams& p, uint32_t g, uint32_t it, bool
       d &= d - 1;
     }
   };
-  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < nq; b0 += gridDim.x * blockDim.x) {
-    const uint32_t q = b0 + threadIdx.x;
-    const uint32_t base = 4 * (q - lane);
-    uint32_t hit;
-    if (dense) {
-      uint64_t m[4];
+  // Each thread takes kStage2Rounds words per pass (one per grid-sized stride), so
+  // that the queue reservation - a block scan, two barriers and an atomic - is paid
+  // once per pass instead of once per grid-sized stride: at 4 M vertices and
+  // sigma = 8 one pass covers the whole graph.
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < nq; b0 += kStage2Rounds * stride) {
+    uint32_t cnt = 0, vb[kStage2Rounds], vn[kStage2Rounds];
+    uint32_t tw[kStage2Rounds];
+    if (!dense) {
+      // the state words of every round first, so that their loads overlap
 #pragma unroll
-      for (uint32_t r = 0; r < 4; ++r) {
-        const uint32_t u = base + r * kWave + lane;
-        uint64_t diff = 0;
-        if (u < G.n) {
-          const ulonglong2 cv = vis2[u];
-          diff = cv.y & ~cv.x;
-          G.front[u] = diff;
-          G.touched[u] = diff ? 2 : 0;
-          if (diff) {
-            G.vis[2 * (uint64_t)u] = cv.y;
-            write_levels(u, diff);
-            grew |= diff;
-          }
-        }
-        m[r] = __ballot(diff != 0);
-      }
-      const uint32_t r = lane >> 4;
-      const uint64_t mr = r == 0 ? m[0] : r == 1 ? m[1] : r == 2 ? m[2] : m[3];
-      hit = (uint32_t)(mr >> ((4 * lane) & 63u)) & 0xFu;
-    } else {
-      const uint32_t tw = q < nq ? tq[q] : 0u;
-      hit = tw & 0x01010101u;
-      if (__ballot(tw != 0)) {
-#pragma unroll
-        for (uint32_t r = 0; r < 4; ++r) {
-          const uint32_t w = (uint32_t)__shfl((int)tw, (int)(r * 16 + (lane >> 2)));
-          const uint32_t b = (w >> (8 * (lane & 3u))) & 0xFFu;
-          const uint32_t u = base + r * kWave + lane;
-          if (b == 2) G.front[u] = 0;
-          if (b & 1u) {
-            const ulonglong2 cv = vis2[u];
-            const uint64_t diff = cv.y & ~cv.x;
-            G.front[u] = diff;
-            G.vis[2 * (uint64_t)u] = cv.y;
-            write_levels(u, diff);
-            grew |= diff;
-          }
-        }
-        if (tw) tq[q] = hit << 1;
+      for (uint32_t j = 0; j < kStage2Rounds; ++j) {
+        const uint32_t q = b0 + j * stride + threadIdx.x;
+        tw[j] = q < nq ? tq[q] : 0u;
       }
     }
-    const uint64_t act = __ballot(hit != 0);
-    uint32_t cnt = 0, vb[1] = {0}, vn[1] = {0};
-    constexpr uint64_t kSetLanes = L == 64 ? ~0ull : ((1ull << L) - 1);
-    if ((lane % L) == 0 && q < nq && ((act >> lane) & kSetLanes)) {
-      const uint32_t ss = q / L;
-      vb[0] = G.real_ptrs[ss];
-      vn[0] = cnt = G.real_ptrs[ss + 1] - vb[0];
+#pragma unroll
+    for (uint32_t j = 0; j < kStage2Rounds; ++j) {
+      const uint32_t q = b0 + j * stride + threadIdx.x;
+      const uint32_t base = 4 * (q - lane);
+      uint32_t hit = 0;
+      if (b0 + j * stride < nq) {  // uniform over the workgroup
+        if (dense) {
+          uint64_t m[4];
+#pragma unroll
+          for (uint32_t r = 0; r < 4; ++r) {
+            const uint32_t u = base + r * kWave + lane;
+            uint64_t diff = 0;
+            if (u < G.n) {
+              const ulonglong2 cv = vis2[u];
+              diff = cv.y & ~cv.x;
+              G.front[u] = diff;
+              G.touched[u] = diff ? 2 : 0;
+              if (diff) {
+                G.vis[2 * (uint64_t)u] = cv.y;
+                write_levels(u, diff);
+                grew |= diff;
+              }
+            }
+            m[r] = __ballot(diff != 0);
+          }
+          const uint32_t r = lane >> 4;
+          const uint64_t mr = r == 0 ? m[0] : r == 1 ? m[1] : r == 2 ? m[2] : m[3];
+          hit = (uint32_t)(mr >> ((4 * lane) & 63u)) & 0xFu;
+        } else {
+          hit = tw[j] & 0x01010101u;
+          if (__ballot(tw[j] != 0)) {
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {
+              const uint32_t w = (uint32_t)__shfl((int)tw[j], (int)(r * 16 + (lane >> 2)));
+              const uint32_t b = (w >> (8 * (lane & 3u))) & 0xFFu;
+              const uint32_t u = base + r * kWave + lane;
+              if (b == 2) G.front[u] = 0;
+              if (b & 1u) {
+                const ulonglong2 cv = vis2[u];
+                const uint64_t diff = cv.y & ~cv.x;
+                G.front[u] = diff;
+                G.vis[2 * (uint64_t)u] = cv.y;
+                write_levels(u, diff);
+                grew |= diff;
+              }
+            }
+            if (tw[j]) tq[q] = hit << 1;
+          }
+        }
+      }
+      const uint64_t act = __ballot(hit != 0);
+      constexpr uint64_t kSetLanes = L == 64 ? ~0ull : ((1ull << L) - 1);
+      vb[j] = vn[j] = 0;
+      if ((lane % L) == 0 && q < nq && ((act >> lane) & kSetLanes)) {
+        const uint32_t ss = q / L;
+        vb[j] = G.real_ptrs[ss];
+        vn[j] = G.real_ptrs[ss + 1] - vb[j];
+        cnt += vn[j];
+      }
     }
     const uint32_t incl = wave_inclusive_scan(cnt);
     if (lane == kWave - 1) s_wave[wave] = incl;
@@ -461,7 +515,7 @@ __device__ void serve_stage2(const ServeParams& p, uint32_t g, uint32_t it, bool
     }
     __syncthreads();
     const uint32_t pos = s_base + s_wave[wave] + incl - cnt;
-    wave_push<1>(qn, pos, cnt, vb, vn);
+    wave_push<kStage2Rounds>(qn, pos, cnt, vb, vn);
     __syncthreads();
   }
   grew = wave_or64(grew);
