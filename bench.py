@@ -704,6 +704,24 @@ def serve_sweep(handles, graphs, rhos, nreq, budget, log_prefix="[bench]", seed_
     edges_of = lambda r: float(sum(comp[r.graph][1][comp[r.graph][0][int(s)]] for s in r.sources))
     src_of = lambda g, seed, k: inputs.sources(graphs[g], seed=seed, k=k)
     srv = Server(handles, budget)
+
+    def idle_stats():
+        # the device-side phase totals are published when a launch ends (idle_ms
+        # after the last request)
+        for _ in range(300):
+            st = srv.dev.stats()
+            if not st["running"]:
+                return st
+            time.sleep(0.01)
+        return srv.dev.stats()
+
+    def phases(a, b):
+        it = max(b["iterations"] - a["iterations"], 1)
+        return {"iterations": b["iterations"] - a["iterations"],
+                **{k.replace("_us", "_us_per_iteration"): round((b[k] - a[k]) / it, 2)
+                   for k in ("control_us", "stage1_us", "stage2_us", "admit_us")}}
+
+    s_prev = idle_stats()
     lone, lone_graph, lone_iters = [], [], []
     for t, gname, s in poisson_trace(99, 1.0, 40, names, src_of):
         r = srv.run([(0.0, gname, s)], realtime=False, keep=False)[0]
@@ -716,20 +734,28 @@ def serve_sweep(handles, graphs, rhos, nreq, budget, log_prefix="[bench]", seed_
                          "iterations": round(float(np.mean([i for _, h, i in warm if h == g])), 1),
                          "us_per_iteration": round(float(np.mean([x / i for x, h, i in warm if h == g])) * 1e6, 2)}
                      for g in names if any(h == g for _, h, _ in warm)}
-    log(f"{log_prefix} mean lone service time {service * 1000:.2f} ms; by graph: {lone_by_graph}")
+    s_now = idle_stats()
+    lone_phases = phases(s_prev, s_now)
+    s_prev = s_now
+    log(f"{log_prefix} mean lone service time {service * 1000:.2f} ms; by graph: {lone_by_graph}; "
+        f"device phases (lone requests): {lone_phases}")
     sweep = []
     for rho in rhos:
         trace = poisson_trace(int(rho * 1000) + 17 + seed_offset, rho / service, nreq, names, src_of)
         reqs = srv.run(trace, keep=False,
                        progress=lambda d, n, rho=rho: log(f"{log_prefix} rho {rho}: {d}/{n} requests done"))
         s = summarize(reqs, edges_of)
+        s_now = idle_stats()
+        s["device_phases"] = phases(s_prev, s_now)
+        s_prev = s_now
         if dump:
             np.savez(f"{dump}_rho{rho}_seed{seed_offset}.npz", latency=np.array([r.latency for r in reqs]),
                      graph=np.array([names.index(r.graph) for r in reqs]), k=np.array([r.k for r in reqs]),
                      edges=np.array([edges_of(r) for r in reqs]), arrival=np.array([r.arrival for r in reqs]),
                      done=np.array([r.done_at for r in reqs]), rate=rho / service, service=service)
         wait = np.array([r.submitted_at - r.arrival for r in reqs]) * 1000.0
-        s.update({"rho": rho, "rate_per_s": round(rho / service, 2), "lone_ms_by_graph": lone_by_graph, "p50_host_wait_ms": float(np.percentile(wait, 50)),
+        s.update({"rho": rho, "rate_per_s": round(rho / service, 2), "lone_ms_by_graph": lone_by_graph,
+                  "lone_device_phases": lone_phases, "p50_host_wait_ms": float(np.percentile(wait, 50)),
                   "p99_host_wait_ms": float(np.percentile(wait, 99)),
                   "budget_waits": int(np.sum(wait > 1.0)), "rejected": 0,
                   "overlapping_pairs": overlapping_pairs(reqs), "peak_output_bytes": srv.peak_bytes,

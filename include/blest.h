@@ -277,6 +277,13 @@ typedef struct {
   uint64_t launches;          /* persistent launches started so far */
   int32_t running;            /* a launch is in flight */
   uint32_t grid, block;       /* launch shape */
+  /* device-side phase times, totals over the launches that have ended (read them
+   * once `running` is 0): server iterations, and microseconds spent in the
+   * control step, in Stage 1 up to its grid barrier (the control step runs beside
+   * the other workgroups' Stage 1), in Stage 2 up to its barrier, and in
+   * admissions */
+  uint64_t iterations;
+  double control_us, stage1_us, stage2_us, admit_us;
 } blest_server_stats_t;
 blest_status blest_server_stats(blest_server_handle s, blest_server_stats_t* out);
 

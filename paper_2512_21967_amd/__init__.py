@@ -41,7 +41,9 @@ EXPORTED_SYMBOLS = ("blest_default_options", "blest_build", "blest_bfs", "blest_
 class ServerStats(ctypes.Structure):
     _fields_ = [("budget", ctypes.c_uint64), ("outstanding", ctypes.c_uint64), ("peak_outstanding", ctypes.c_uint64),
                 ("resident_bytes", ctypes.c_uint64), ("submitted", ctypes.c_uint64), ("launches", ctypes.c_uint64),
-                ("running", ctypes.c_int32), ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32)]
+                ("running", ctypes.c_int32), ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32),
+                ("iterations", ctypes.c_uint64), ("control_us", ctypes.c_double), ("stage1_us", ctypes.c_double),
+                ("stage2_us", ctypes.c_double), ("admit_us", ctypes.c_double)]
 
 
 class BlestError(RuntimeError):

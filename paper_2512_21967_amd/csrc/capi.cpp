@@ -322,7 +322,10 @@ blest_status set_grid(blest_graph* g) {
     g->range_words = cache_shape(g->range_len / 32, std::min<uint32_t>(g->lds_cap_words, (uint32_t)room),
                                  g->lds_cshift);
     if (g->range_words == 0) return BLEST_ERR_DEVICE;
-    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * g->range_words)) != hipSuccess)
+    // the attribute belongs to the kernel, not to this graph: it is set to all the
+    // room there is, so that a graph with a smaller cache built later does not
+    // shrink it below what this one launches with
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * room)) != hipSuccess)
       return BLEST_ERR_DEVICE;
   }
   const uint32_t dyn = lds ? 4 * g->range_words : 0;
@@ -1266,6 +1269,13 @@ blest_status blest_server_stats(blest_server_handle sv, blest_server_stats_t* ou
   out->running = sv->launched && hipEventQuery(sv->ev) == hipErrorNotReady;
   out->grid = sv->grid;
   out->block = sv->block;
+  // the mailbox is coherent host memory; the kernel writes these when a launch ends
+  volatile const uint64_t* prof = sv->mb->prof;
+  out->iterations = prof[4];
+  out->control_us = prof[0] * 0.01;  // 100 MHz realtime ticks
+  out->stage1_us = prof[1] * 0.01;
+  out->stage2_us = prof[2] * 0.01;
+  out->admit_us = prof[3] * 0.01;
   return BLEST_OK;
 }
 

@@ -118,7 +118,12 @@ struct ServeSlot {
 struct ServeMailbox {
   uint32_t submitted;  // tickets [0, submitted) are published (host writes)
   uint32_t stop;       // host: 1 = end the launch once no request is waiting or running
-  uint32_t pad[30];
+  uint32_t pad0[2];
+  // totals over all launches so far, written when a launch ends: realtime ticks
+  // (100 MHz) spent in the control step, in Stage 1 up to its grid barrier, in
+  // Stage 2 up to its barrier and in admissions, and the iteration count
+  uint64_t prof[5];
+  uint32_t pad[18];
   ServeSlot slot[kServeRing];
 };
 
@@ -145,6 +150,7 @@ struct ServeState {
   uint32_t n_admit;    // columns admitted at this level boundary
   uint32_t launches;   // launches that started
   uint32_t pad0[2];
+  uint64_t prof[5];    // running totals of ServeMailbox::prof
   unsigned long long active[kServeMaxGraphs];  // columns in use
   unsigned long long alive[kServeMaxGraphs];   // columns that grew in the last iteration
   unsigned long long dirty[kServeMaxGraphs];   // freed columns whose bits are still set

@@ -36,7 +36,7 @@
 namespace blest {
 namespace {
 
-constexpr uint64_t kDenseFrac = 16;  // dense Stage 2 when the queue holds >= 1/16 of the VSSs
+constexpr uint64_t kDenseFrac = 1;  // dense Stage 2 only when the queue holds every VSS
 constexpr uint32_t kStage2Rounds = 4;  // words per thread and pass of Stage 2
 
 __device__ __forceinline__ uint32_t sys_load(const uint32_t* p) {
@@ -349,44 +349,73 @@ __device__ void serve_stage1(const ServeParams& p, uint32_t it, const uint32_t (
       ms = G.v2r[v];
     }
     const uint32_t cnt = min((uint32_t)kWave, (total - base + nw - 1) / nw);
-    for (uint32_t k = 0; k < cnt; ++k) {
-      const uint32_t g = readlane(mg, k);
-      const ServeGraph& G = p.g[g];
-      const bool mark = !((dense >> g) & 1u);
-      const MT* masks = static_cast<const MT*>(G.masks);
-      const uint32_t beg = readlane(mb, k), end = readlane(me, k), ss = readlane(ms, k);
-      const uint32_t col = ss * SIG + lane;
-      const uint64_t bw = (lane < (uint32_t)SIG && col < G.n) ? G.front[col] : 0ull;
-      uint64_t B[SIG];
+    // Two VSSs per step at sigma <= 16 (possibly of different graphs): the B-tile
+    // and slice loads of both, then their visited-pair reads, are issued before
+    // either is applied, which halves the chain of dependent round trips per VSS.
+    // At sigma = 32 two B tiles would not fit the scalar registers.
+    constexpr uint32_t P = SIG <= 16 ? 2 : 1;
+    for (uint32_t k0 = 0; k0 < cnt; k0 += P) {
+      uint32_t gg[P], beg[P], end[P], ss[P];
 #pragma unroll
-      for (int j = 0; j < SIG; ++j) B[j] = readlane64(bw, j);
-      MT m[SLOTS];
-      uint32_t u[SLOTS];
-#pragma unroll
-      for (int r = 0; r < SLOTS; ++r) {
-        const uint32_t idx = beg + lane + r * kWave;
-        const bool ok = idx < end;
-        m[r] = ok ? masks[idx] : MT(0);
-        u[r] = ok ? G.row_ids[idx] : 0u;
+      for (uint32_t h = 0; h < P; ++h) {
+        const bool any = k0 + h < cnt;
+        const uint32_t k = any ? k0 + h : k0;
+        gg[h] = readlane(mg, k);
+        beg[h] = readlane(mb, k);
+        end[h] = any ? readlane(me, k) : beg[h];  // past the end: an empty VSS
+        ss[h] = readlane(ms, k);
       }
-      uint64_t acc[SLOTS];
-      ulonglong2 cv[SLOTS];
+      uint64_t bw[P];
 #pragma unroll
-      for (int r = 0; r < SLOTS; ++r) {
-        uint64_t a = 0;
+      for (uint32_t h = 0; h < P; ++h) {
+        const ServeGraph& G = p.g[gg[h]];
+        const uint32_t col = ss[h] * SIG + lane;
+        bw[h] = (lane < (uint32_t)SIG && col < G.n && end[h] > beg[h]) ? G.front[col] : 0ull;
+      }
+      MT m[P][SLOTS];
+      uint32_t u[P][SLOTS];
 #pragma unroll
-        for (int j = 0; j < SIG; ++j) a |= ((uint32_t)m[r] >> j & 1u) ? B[j] : 0ull;
-        acc[r] = a;
-        cv[r] = reinterpret_cast<const ulonglong2*>(G.vis)[a ? u[r] : 0u];
+      for (uint32_t h = 0; h < P; ++h) {
+        const ServeGraph& G = p.g[gg[h]];
+        const MT* masks = static_cast<const MT*>(G.masks);
+#pragma unroll
+        for (int r = 0; r < SLOTS; ++r) {
+          const uint32_t idx = beg[h] + lane + r * kWave;
+          const bool ok = idx < end[h];
+          m[h][r] = ok ? masks[idx] : MT(0);
+          u[h][r] = ok ? G.row_ids[idx] : 0u;
+        }
+      }
+      uint64_t acc[P][SLOTS];
+      ulonglong2 cv[P][SLOTS];
+#pragma unroll
+      for (uint32_t h = 0; h < P; ++h) {
+        const ServeGraph& G = p.g[gg[h]];
+        uint64_t B[SIG];
+#pragma unroll
+        for (int j = 0; j < SIG; ++j) B[j] = readlane64(bw[h], j);
+#pragma unroll
+        for (int r = 0; r < SLOTS; ++r) {
+          uint64_t a = 0;
+#pragma unroll
+          for (int j = 0; j < SIG; ++j) a |= ((uint32_t)m[h][r] >> j & 1u) ? B[j] : 0ull;
+          acc[h][r] = a;
+          cv[h][r] = reinterpret_cast<const ulonglong2*>(G.vis)[a ? u[h][r] : 0u];
+        }
       }
 #pragma unroll
-      for (int r = 0; r < SLOTS; ++r) {
-        const uint64_t fresh = acc[r] & ~cv[r].x & ~cv[r].y;
-        if (fresh) {
-          atomicOr(G.vis + 2 * (uint64_t)u[r] + 1, (unsigned long long)fresh);
-          // the first OR that changes u's next word was issued by a thread that read
-          // next == current (every iteration starts with them equal)
-          if (mark && cv[r].y == cv[r].x) G.touched[u[r]] = 1;
+      for (uint32_t h = 0; h < P; ++h) {
+        const ServeGraph& G = p.g[gg[h]];
+        const bool mark = !((dense >> gg[h]) & 1u);
+#pragma unroll
+        for (int r = 0; r < SLOTS; ++r) {
+          const uint64_t fresh = acc[h][r] & ~cv[h][r].x & ~cv[h][r].y;
+          if (fresh) {
+            atomicOr(G.vis + 2 * (uint64_t)u[h][r] + 1, (unsigned long long)fresh);
+            // the first OR that changes u's next word was issued by a thread that read
+            // next == current (every iteration starts with them equal)
+            if (mark && cv[h][r].y == cv[h][r].x) G.touched[u[h][r]] = 1;
+          }
         }
       }
     }
@@ -401,6 +430,7 @@ __device__ void serve_stage2(const ServeParams& p, uint32_t g, uint32_t it, bool
   __shared__ uint32_t s_base;
   __shared__ uint64_t s_out[kServeCols];
   __shared__ uint32_t s_lvl[kServeCols];
+  __shared__ unsigned long long s_grew;
   const ServeGraph& G = p.g[g];
   ServeState* st = p.st;
   const uint32_t lane = lane_id();
@@ -409,6 +439,7 @@ __device__ void serve_stage2(const ServeParams& p, uint32_t g, uint32_t it, bool
     s_out[threadIdx.x] = st->col_out[g][threadIdx.x];
     s_lvl[threadIdx.x] = it + 1 - st->col_start[g][threadIdx.x];
   }
+  if (threadIdx.x == 0) s_grew = 0;
   __syncthreads();
   const uint32_t nq = G.num_sets * L;
   uint32_t* tq = reinterpret_cast<uint32_t*>(G.touched);
@@ -518,8 +549,12 @@ __device__ void serve_stage2(const ServeParams& p, uint32_t g, uint32_t it, bool
     wave_push<kStage2Rounds>(qn, pos, cnt, vb, vn);
     __syncthreads();
   }
+  // the columns that grew, ORed within the workgroup first: one device atomic per
+  // workgroup instead of one per wavefront on a single word
   grew = wave_or64(grew);
-  if (lane == 0 && grew) atomicOr(&st->alive[g], (unsigned long long)grew);
+  if (lane == 0 && grew) atomicOr(&s_grew, (unsigned long long)grew);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_grew) atomicOr(&st->alive[g], s_grew);
   __syncthreads();  // s_out / s_lvl are reloaded for the next graph
 }
 
@@ -542,19 +577,39 @@ __global__ __launch_bounds__(1024) void serve_persistent(ServeParams p) {
       if ((uint64_t)len[g] * kDenseFrac >= p.g[g].num_vss) dense |= 1u << g;
     }
     // the control wavefront first settles finished and new requests, then joins
-    // Stage 1 (whose queue it does not change)
+    // Stage 1 (whose queue it does not change).  Thread 0, in that wavefront, keeps
+    // the phase times.
+    const uint64_t t0 = tid == 0 ? __builtin_amdgcn_s_memrealtime() : 0;
     if (blockIdx.x == 0 && threadIdx.x < kWave) serve_control(p, it);
+    const uint64_t tc = tid == 0 ? __builtin_amdgcn_s_memrealtime() : 0;
     serve_stage1<MT, SLOTS>(p, it, len, dense);
     grid_barrier(ctrl);
-    if (st->exit) break;
+    const uint64_t t1 = tid == 0 ? __builtin_amdgcn_s_memrealtime() : 0;
+    if (st->exit) {
+      if (tid == 0) {
+        st->prof[0] += tc - t0;
+        for (int i = 0; i < 5; ++i) p.mb->prof[i] = st->prof[i];
+        __threadfence_system();
+      }
+      break;
+    }
     for (uint32_t g = 0; g < p.ngraphs; ++g)
       if (st->active[g]) serve_stage2<SIG>(p, g, it, (dense >> g) & 1u);
     grid_barrier(ctrl);
+    const uint64_t t2 = tid == 0 ? __builtin_amdgcn_s_memrealtime() : 0;
     if (st->n_admit) {
       serve_init_a(p);
       grid_barrier(ctrl);
       serve_init_b<SIG>(p, it);
       grid_barrier(ctrl);
+    }
+    if (tid == 0) {
+      const uint64_t t3 = __builtin_amdgcn_s_memrealtime();
+      st->prof[0] += tc - t0;
+      st->prof[1] += t1 - tc;
+      st->prof[2] += t2 - t1;
+      st->prof[3] += t3 - t2;
+      st->prof[4] += 1;
     }
   }
 }
