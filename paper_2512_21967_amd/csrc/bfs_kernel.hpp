@@ -465,6 +465,17 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint2* qn, uint3
       const uint32_t diff = reached & ~cur;
       if (diff) {
         p.vis[t] = cur | diff;
+        // the VSS ranges of the sets with new vertices are loaded before the level
+        // stores, so that their round trip overlaps that of the original IDs
+#pragma unroll
+        for (int i = 0; i < SPW; ++i) {
+          va[i] = (diff >> (i * SIG)) & chunk_mask<SIG>();
+          if (va[i]) {
+            const uint32_t ss = t * SPW + i;
+            vb[i] = p.real_ptrs[ss];
+            vn[i] = p.real_ptrs[ss + 1] - vb[i];
+          }
+        }
         // levels of the new vertices: their original IDs are loaded 8 at a time
         // (two 16-byte loads) so that the stores do not wait one by one
 #pragma unroll
@@ -485,15 +496,7 @@ __device__ __forceinline__ void stage2_lazy(const BfsParams& p, uint2* qn, uint3
             if (d8 & (1u << j)) p.levels[o[j]] = level;
         }
 #pragma unroll
-        for (int i = 0; i < SPW; ++i) {
-          va[i] = (diff >> (i * SIG)) & chunk_mask<SIG>();
-          if (va[i]) {
-            const uint32_t ss = t * SPW + i;
-            vb[i] = p.real_ptrs[ss];
-            vn[i] = p.real_ptrs[ss + 1] - vb[i];
-            cnt += vn[i];
-          }
-        }
+        for (int i = 0; i < SPW; ++i) cnt += vn[i];
       }
     }
     const uint32_t incl = wave_inclusive_scan(cnt);

@@ -166,24 +166,33 @@ __device__ __forceinline__ void multi_stage2(const MultiParams& p, uint32_t* qn,
     const uint32_t base = 4 * (q - lane);
     uint32_t hit;  // per word: nonzero iff one of its four vertices changed
     if (dense) {
-      // full sweep: every vertex, state bytes rewritten (Stage 1 stored none)
+      // full sweep: every vertex, state bytes rewritten (Stage 1 stored none).  The
+      // four vertices' loads come first: a store to the visited pairs between them
+      // would order each load after the previous vertex's round trip.
+      ulonglong2 cv[4];
+      uint32_t uo[4];
+#pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t u = base + r * kWave + lane;
+        const uint32_t ui = u < p.n ? u : 0u;
+        cv[r] = vis2[ui];
+        uo[r] = morig(p, ui);
+      }
       uint64_t m[4];
 #pragma unroll
       for (uint32_t r = 0; r < 4; ++r) {
         const uint32_t u = base + r * kWave + lane;
         uint64_t diff = 0;
         if (u < p.n) {
-          const ulonglong2 cv = vis2[u];
-          diff = cv.y & ~cv.x;
+          diff = cv[r].y & ~cv[r].x;
           p.front[u] = diff;
           p.touched[u] = diff ? 2 : 0;
           if (diff) {
-            p.vis[2 * (uint64_t)u] = cv.y;
-            const uint32_t uo = morig(p, u);
+            p.vis[2 * (uint64_t)u] = cv[r].y;
             uint64_t d = diff;
             while (d) {
               const uint32_t jj = __ffsll((unsigned long long)d) - 1;
-              p.levels[(uint64_t)jj * p.n + uo] = level;
+              p.levels[(uint64_t)jj * p.n + uo[r]] = level;
               d &= d - 1;
             }
           }
@@ -197,22 +206,30 @@ __device__ __forceinline__ void multi_stage2(const MultiParams& p, uint32_t* qn,
       const uint32_t tw = q < nq ? tq[q] : 0u;
       hit = tw & 0x01010101u;  // touched this level
       if (__ballot(tw != 0)) {
+        // loads of the four vertices first (index 0 for an untouched one), then the
+        // stores, so that the round trips overlap
+        uint32_t bb[4], uo[4];
+        ulonglong2 cv[4];
 #pragma unroll
         for (uint32_t r = 0; r < 4; ++r) {
           const uint32_t w = (uint32_t)__shfl((int)tw, (int)(r * 16 + (lane >> 2)));
-          const uint32_t b = (w >> (8 * (lane & 3u))) & 0xFFu;
+          bb[r] = (w >> (8 * (lane & 3u))) & 0xFFu;
+          const uint32_t ui = (bb[r] & 1u) ? base + r * kWave + lane : 0u;
+          cv[r] = vis2[ui];
+          uo[r] = morig(p, ui);
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
           const uint32_t u = base + r * kWave + lane;
-          if (b == 2) p.front[u] = 0;  // left the frontier
-          if (b & 1u) {
-            const ulonglong2 cv = vis2[u];
-            const uint64_t diff = cv.y & ~cv.x;
+          if (bb[r] == 2) p.front[u] = 0;  // left the frontier
+          if (bb[r] & 1u) {
+            const uint64_t diff = cv[r].y & ~cv[r].x;
             p.front[u] = diff;
-            p.vis[2 * (uint64_t)u] = cv.y;
-            const uint32_t uo = morig(p, u);
+            p.vis[2 * (uint64_t)u] = cv[r].y;
             uint64_t d = diff;
             while (d) {
               const uint32_t jj = __ffsll((unsigned long long)d) - 1;
-              p.levels[(uint64_t)jj * p.n + uo] = level;
+              p.levels[(uint64_t)jj * p.n + uo[r]] = level;
               d &= d - 1;
             }
           }

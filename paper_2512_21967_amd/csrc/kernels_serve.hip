@@ -447,8 +447,7 @@ __device__ void serve_stage2(const ServeParams& p, uint32_t g, uint32_t it, bool
   uint32_t* qlen = qlen_of(p, g, it % 3);
   uint32_t* qn = G.queue + (it & 1) * G.qcap;
   uint64_t grew = 0;
-  auto write_levels = [&](uint32_t u, uint64_t diff) {
-    const uint32_t uo = sorig(G, u);
+  auto write_levels = [&](uint32_t uo, uint64_t diff) {
     uint64_t d = diff;
     while (d) {
       const uint32_t c = __ffsll((unsigned long long)d) - 1;
@@ -479,19 +478,29 @@ __device__ void serve_stage2(const ServeParams& p, uint32_t g, uint32_t it, bool
       uint32_t hit = 0;
       if (b0 + j * stride < nq) {  // uniform over the workgroup
         if (dense) {
+          // the four vertices' loads first: a store to the visited pairs between
+          // them would order each load after the previous vertex's round trip
+          ulonglong2 cv[4];
+          uint32_t uo[4];
+#pragma unroll
+          for (uint32_t r = 0; r < 4; ++r) {
+            const uint32_t u = base + r * kWave + lane;
+            const uint32_t ui = u < G.n ? u : 0u;
+            cv[r] = vis2[ui];
+            uo[r] = sorig(G, ui);
+          }
           uint64_t m[4];
 #pragma unroll
           for (uint32_t r = 0; r < 4; ++r) {
             const uint32_t u = base + r * kWave + lane;
             uint64_t diff = 0;
             if (u < G.n) {
-              const ulonglong2 cv = vis2[u];
-              diff = cv.y & ~cv.x;
+              diff = cv[r].y & ~cv[r].x;
               G.front[u] = diff;
               G.touched[u] = diff ? 2 : 0;
               if (diff) {
-                G.vis[2 * (uint64_t)u] = cv.y;
-                write_levels(u, diff);
+                G.vis[2 * (uint64_t)u] = cv[r].y;
+                write_levels(uo[r], diff);
                 grew |= diff;
               }
             }
@@ -503,18 +512,27 @@ __device__ void serve_stage2(const ServeParams& p, uint32_t g, uint32_t it, bool
         } else {
           hit = tw[j] & 0x01010101u;
           if (__ballot(tw[j] != 0)) {
+            // loads of the four vertices first (index 0 for an untouched one), then
+            // the stores, so that the round trips overlap
+            uint32_t bb[4], uo[4];
+            ulonglong2 cv[4];
 #pragma unroll
             for (uint32_t r = 0; r < 4; ++r) {
               const uint32_t w = (uint32_t)__shfl((int)tw[j], (int)(r * 16 + (lane >> 2)));
-              const uint32_t b = (w >> (8 * (lane & 3u))) & 0xFFu;
+              bb[r] = (w >> (8 * (lane & 3u))) & 0xFFu;
+              const uint32_t ui = (bb[r] & 1u) ? base + r * kWave + lane : 0u;
+              cv[r] = vis2[ui];
+              uo[r] = sorig(G, ui);
+            }
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {
               const uint32_t u = base + r * kWave + lane;
-              if (b == 2) G.front[u] = 0;
-              if (b & 1u) {
-                const ulonglong2 cv = vis2[u];
-                const uint64_t diff = cv.y & ~cv.x;
+              if (bb[r] == 2) G.front[u] = 0;
+              if (bb[r] & 1u) {
+                const uint64_t diff = cv[r].y & ~cv[r].x;
                 G.front[u] = diff;
-                G.vis[2 * (uint64_t)u] = cv.y;
-                write_levels(u, diff);
+                G.vis[2 * (uint64_t)u] = cv[r].y;
+                write_levels(uo[r], diff);
                 grew |= diff;
               }
             }
