@@ -114,12 +114,19 @@ def test_idle_launch_ends_and_restarts(resident):
     graphs, handles = resident
     import time
     srv = Server(handles, 64 << 20, idle_ms=5)
+    iters = 0
     for round_ in range(3):
         s = inputs.sources(graphs["small"], seed=round_, k=5)
         reqs = srv.run([(0.0, "small", s)], keep=False, on_done=to_host)
         np.testing.assert_array_equal(reqs[0].host, oracle.bfs_multi(graphs["small"], s))
+        iters += reqs[0].done_iter - reqs[0].admit_iter + 1
         time.sleep(0.05)  # the launch ends after 5 ms without work
-        assert not srv.dev.stats()["running"]
+        st = srv.dev.stats()
+        assert not st["running"]
+        # the phase totals are published when a launch ends: every iteration that
+        # ran a request is counted, and every phase took some time
+        assert st["iterations"] >= iters
+        assert min(st["control_us"], st["stage1_us"], st["stage2_us"], st["admit_us"]) > 0
     assert srv.dev.stats()["launches"] >= 3
     srv.close()
     # ordinary calls run again after the server's launches ended
