@@ -200,7 +200,7 @@ def run_single(args):
         opts.update(tuned)
     if args.window:
         opts["window"] = args.window
-    for k in ("block", "blocks_per_cu", "lds_kib"):
+    for k in ("block", "blocks_per_cu", "lds_kib", "max_grid"):
         if getattr(args, k):
             opts[k] = getattr(args, k)
     g = blest.Graph(gr, device=0, ranges=args.ranges, prepass=args.prepass, **opts)
@@ -280,7 +280,7 @@ def run_single(args):
               "eager_max": st["eager_max"] if st["update_used"] == "adaptive" else None, "group": opts.get("group", 2),
               "slots": st["tau"] // 64, "tuned": {"key": tuned_key, "options": tuned} if tuned else None}
     # the latency bound: every level costs at least its grid barriers
-    t_bar = blest.barrier_seconds(0, st["block"])
+    t_bar = blest.barrier_seconds(0, st["block"], max_grid=st["grid"])
     nbar = np.array([barrier_count(g, st, gpu_or_none) for gpu_or_none in lat_levels], dtype=np.float64)
     t_lat = nbar.mean() * t_bar
     t_hbm = mb.mean() / (HBM_PEAK_GBS * 1e9)
@@ -849,6 +849,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: the library default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="workgroups per CU (0: the library default)")
     ap.add_argument("--lds-kib", type=int, default=0, help="LDS visited cache per workgroup (0: auto)")
+    ap.add_argument("--max-grid", type=int, default=0, help="cap on the single-source grid (0: the tuned or full grid)")
     ap.add_argument("--window", type=int, default=0, help="Algorithm 1 window (0: the library default)")
     ap.add_argument("--prepass", default="auto", choices=["auto", "off", "shingle"],
                     help="locality pre-pass before Algorithm 1 (single-source workloads)")

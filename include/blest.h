@@ -109,6 +109,9 @@ typedef struct {
   uint64_t shingle_seed; /* seed of its hash functions: h_i(u) is output u + 1 of the SplitMix64 stream
                           (Steele, Lea and Flood, OOPSLA 2014) seeded with output i + 1 of the stream
                           seeded with shingle_seed (default 0x243F6A8885A308D3) */
+  uint32_t max_grid;   /* cap on the workgroups of the single-source persistent launch (0 = every
+                          co-resident one).  A smaller grid pays a cheaper grid barrier per level, which
+                          suits graphs with thousands of small levels (high diameter) */
 } blest_options;
 
 #define BLEST_LDS_OFF 0xFFFFFFFFu
@@ -363,12 +366,14 @@ blest_status blest_level_stats(int32_t device, const int32_t* levels, uint32_t k
 blest_status blest_model_bytes(blest_handle h, const int32_t* levels, uint32_t k, uint64_t* bytes);
 
 /* Measures the grid barrier of the persistent launches (one workgroup of `block`
- * threads per compute unit): a launch doing `rounds` barriers and nothing else,
- * timed with HIP events after a warm-up run; *seconds_per_barrier = time /
+ * threads per compute unit, at most max_grid workgroups when max_grid > 0, as
+ * blest_options.max_grid caps them): a launch doing `rounds` barriers and nothing
+ * else, timed with HIP events after a warm-up run; *seconds_per_barrier = time /
  * rounds.  For the latency bound of high-diameter graphs, where every level costs
  * at least one barrier.  Synchronous; allocates a small control block.
  * Errors: INVALID_ARGUMENT, NO_DEVICE, DEVICE. */
-blest_status blest_barrier_probe(int32_t device, uint32_t block, uint32_t rounds, double* seconds_per_barrier);
+blest_status blest_barrier_probe(int32_t device, uint32_t block, uint32_t max_grid, uint32_t rounds,
+                                 double* seconds_per_barrier);
 
 /* Releases the library's process-wide HIP objects once the work using them has
  * finished: the per-device events that order persistent launches and the item

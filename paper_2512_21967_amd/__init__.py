@@ -59,7 +59,7 @@ class Options(ctypes.Structure):
                 ("group", ctypes.c_uint32), ("ranges", ctypes.c_uint32), ("hubs", ctypes.c_uint32),
                 ("lds_kib", ctypes.c_uint32), ("eager_max", ctypes.c_uint32), ("pack", ctypes.c_uint32),
                 ("multi_ranges", ctypes.c_uint32), ("prepass", ctypes.c_uint32), ("shingles", ctypes.c_uint32),
-                ("shingle_seed", ctypes.c_uint64)]
+                ("shingle_seed", ctypes.c_uint64), ("max_grid", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -143,7 +143,7 @@ def lib():
     L.blest_model_bytes.restype = ctypes.c_int
     L.blest_level_stats.argtypes = [i32, vp, u32, u32, vp, vp, vp, vp, vp, vp]
     L.blest_level_stats.restype = ctypes.c_int
-    L.blest_barrier_probe.argtypes = [i32, u32, u32, ctypes.POINTER(ctypes.c_double)]
+    L.blest_barrier_probe.argtypes = [i32, u32, u32, u32, ctypes.POINTER(ctypes.c_double)]
     L.blest_barrier_probe.restype = ctypes.c_int
     L.blest_shutdown.argtypes = []
     L.blest_shutdown.restype = None
@@ -195,7 +195,8 @@ class Graph:
 
     def __init__(self, csr, *, sigma=8, slots=2, window=0, reorder="auto", update="auto",
                  device=0, threads=0, block=0, blocks_per_cu=0, group=0, ranges=0, hubs="auto", lds_kib=0,
-                 eager_max=0, pack=True, multi_ranges=0, prepass="auto", shingles=0, shingle_seed=None):
+                 eager_max=0, pack=True, multi_ranges=0, prepass="auto", shingles=0, shingle_seed=None,
+                 max_grid=0):
         o = default_options()
         o.sigma, o.slots, o.window = sigma, slots, window
         o.reorder, o.update = REORDER[reorder], UPDATE[update]
@@ -208,6 +209,7 @@ class Graph:
         o.prepass, o.shingles = PREPASS[prepass], shingles
         if shingle_seed is not None:
             o.shingle_seed = shingle_seed
+        o.max_grid = max_grid
         rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint32)
         col = np.ascontiguousarray(csr.col if len(csr.col) else np.zeros(1, np.uint32), dtype=np.uint32)
         h = ctypes.c_void_p()
@@ -389,10 +391,12 @@ def level_stats(levels, stream=None) -> dict:
             "closeness": close}
 
 
-def barrier_seconds(device: int = 0, block: int = 1024, rounds: int = 2000) -> float:
-    """Seconds per grid barrier of the persistent launches (blest_barrier_probe)."""
+def barrier_seconds(device: int = 0, block: int = 1024, rounds: int = 2000, max_grid: int = 0) -> float:
+    """Seconds per grid barrier of the persistent launches (blest_barrier_probe),
+    over at most max_grid workgroups when max_grid > 0."""
     x = ctypes.c_double()
-    _check("blest_barrier_probe", lib().blest_barrier_probe(int(device), int(block), int(rounds), ctypes.byref(x)))
+    _check("blest_barrier_probe", lib().blest_barrier_probe(int(device), int(block), int(max_grid), int(rounds),
+                                                            ctypes.byref(x)))
     return float(x.value)
 
 

@@ -45,10 +45,14 @@ class Trial:
     update: str
     ms: float                      # median over repeats of one round (all sources)
     eager_max: int = 0             # adaptive threshold (0 = the library's default)
+    max_grid: int = 0              # cap on the single-source grid (0 = every co-resident workgroup)
 
     def options(self) -> dict:
-        return {"sigma": self.sigma, "slots": self.slots, "group": self.group, "update": self.update,
-                "eager_max": self.eager_max}
+        o = {"sigma": self.sigma, "slots": self.slots, "group": self.group, "update": self.update,
+             "eager_max": self.eager_max}
+        if self.max_grid:
+            o["max_grid"] = self.max_grid
+        return o
 
 
 def graph_key(csr, k: int = 1) -> str:
@@ -104,12 +108,14 @@ def _round(g, sources, k, stream):
     return [g.bfs_multi(np.asarray(sources, np.uint32), stream=stream)]
 
 
-def autotune(csr, sources, *, k=1, cands=None, repeats=3, reorder="auto", window=0, device=0, log=None):
+def autotune(csr, sources, *, k=1, cands=None, repeats=3, reorder="auto", window=0, device=0, log=None,
+             max_grids=(0,)):
     """Times every candidate on `sources` and returns (best Trial, [Trial...]).
 
     k = 1 times one single-source BFS per source; k > 1 times one k-source call on
     the first k sources.  The builds use the same ordering options, so the
-    candidates differ only in layout and launch settings."""
+    candidates differ only in layout and launch settings.  max_grids: caps on the
+    single-source grid to try with every candidate (a build option; 0 = none)."""
     import torch
     import paper_2512_21967_amd as blest
 
@@ -121,9 +127,11 @@ def autotune(csr, sources, *, k=1, cands=None, repeats=3, reorder="auto", window
     trials, ref = [], None
     by_layout = {}
     for c in cands:
-        by_layout.setdefault((c[0], c[1]), []).append(c)
-    for (sg, sl), group in by_layout.items():
-        g = blest.Graph(csr, sigma=sg, slots=sl, window=window - window % sg, reorder=reorder, device=device)
+        for mg in (max_grids if k == 1 else (0,)):
+            by_layout.setdefault((c[0], c[1], mg), []).append(c)
+    for (sg, sl, mg), group in by_layout.items():
+        g = blest.Graph(csr, sigma=sg, slots=sl, window=window - window % sg, reorder=reorder, device=device,
+                        max_grid=mg)
         for _, _, gr, up, em in group:
             g.configure(update=up, group=gr, eager_max=em)
             outs = _round(g, src, k, stream)          # warm-up (and workspace allocation)
@@ -141,10 +149,10 @@ def autotune(csr, sources, *, k=1, cands=None, repeats=3, reorder="auto", window
                 b.record(stream)
                 b.synchronize()
                 times.append(a.elapsed_time(b))
-            t = Trial(sg, sl, gr, up, float(np.median(times)), em)
+            t = Trial(sg, sl, gr, up, float(np.median(times)), em, mg)
             trials.append(t)
             if log:
-                log(f"[autotune] sigma={sg} slots={sl} group={gr} {up} eager_max={em}: {t.ms:.3f} ms")
+                log(f"[autotune] sigma={sg} slots={sl} group={gr} {up} eager_max={em} max_grid={mg}: {t.ms:.3f} ms")
         g.close()
     best = min(trials, key=lambda t: t.ms)
     return best, trials
@@ -155,7 +163,7 @@ def autotune(csr, sources, *, k=1, cands=None, repeats=3, reorder="auto", window
 WORKLOADS = {
     "rmat22": dict(cands=candidates((8,), (1, 2, 4), (1, 2), ("lazy", "adaptive"), (0, 4096, 131072)),
                    k=1, nsrc=16),
-    "grid4096": dict(cands=candidates((8,), (1, 2), (1, 2), ("eager", "adaptive"), (0,)), k=1, nsrc=4),
+    "grid4096": dict(cands=candidates((8,), (1, 2), (1, 2), ("eager",), (0,)), k=1, nsrc=4, max_grids=(0, 64, 32)),
     "rmat16": dict(cands=candidates((8, 16), (1, 2, 4), (1, 2), UPDATES, (0, 256)), k=1, nsrc=16),
     "rmat20x64": dict(cands=candidates((8, 16, 32), (1, 2, 4), (2,), ("lazy",), (0,)), k=64, nsrc=64),
 }
@@ -183,7 +191,8 @@ def main():
         gr, reorder = inputs.rmat_workload(20, 16, seed=1), "none"
         src = inputs.sources(gr, seed=7, k=64, distinct=True)
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    best, trials = autotune(gr, src, k=w["k"], cands=w["cands"], repeats=args.repeats, reorder=reorder, log=log)
+    best, trials = autotune(gr, src, k=w["k"], cands=w["cands"], repeats=args.repeats, reorder=reorder, log=log,
+                            max_grids=w.get("max_grids", (0,)))
     key = graph_key(gr, w["k"])
     save(key, best, trials, args.workload, path=args.out)
     print(json.dumps({"key": key, "best": best.options(), "ms": best.ms}), flush=True)

@@ -336,6 +336,8 @@ blest_status set_grid(blest_graph* g) {
   g->occ_own = own_blocks_per_cu(k, g->block, dyn, &g->num_regs);
   const uint32_t per_cu = std::min({(uint32_t)nb, g->occ_own, g->opt.blocks_per_cu});
   g->grid = per_cu * (uint32_t)cus / g->nranges * g->nranges;
+  if (g->opt.max_grid && g->grid > g->opt.max_grid)
+    g->grid = std::max(g->nranges, g->opt.max_grid / g->nranges * g->nranges);
   if (g->grid == 0) return BLEST_ERR_DEVICE;
   const void* km = bfs_multi_kernel_symbol(b.sigma, b.slots);
   int nbm = 0, regs_m = 0;
@@ -504,6 +506,7 @@ void blest_default_options(blest_options* o) {
   o->prepass = 0;
   o->shingles = 0;
   o->shingle_seed = 0x243F6A8885A308D3ull;
+  o->max_grid = 0;
 }
 
 blest_status blest_build(uint32_t n, uint64_t nnz, const uint32_t* row_ptr, const uint32_t* col_idx,
@@ -1304,7 +1307,8 @@ blest_status blest_server_destroy(blest_server_handle sv, uint32_t timeout_ms) {
   return BLEST_OK;
 }
 
-blest_status blest_barrier_probe(int32_t device, uint32_t block, uint32_t rounds, double* seconds_per_barrier) {
+blest_status blest_barrier_probe(int32_t device, uint32_t block, uint32_t max_grid, uint32_t rounds,
+                                 double* seconds_per_barrier) {
   if (!seconds_per_barrier || rounds == 0 || block == 0 || block % 64 != 0 || block > 1024)
     return BLEST_ERR_INVALID_ARGUMENT;
   int count = 0;
@@ -1316,7 +1320,8 @@ blest_status blest_barrier_probe(int32_t device, uint32_t block, uint32_t rounds
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)block, 0) != hipSuccess || nb <= 0)
     return BLEST_ERR_DEVICE;
   // one workgroup per CU, as the BFS launches of that workgroup size
-  const uint32_t grid = std::min<uint32_t>({(uint32_t)nb, own_blocks_per_cu(k, block, 0, &regs), 1u}) * (uint32_t)cus;
+  uint32_t grid = std::min<uint32_t>({(uint32_t)nb, own_blocks_per_cu(k, block, 0, &regs), 1u}) * (uint32_t)cus;
+  if (max_grid && grid > max_grid) grid = max_grid;
   DevBuf ctrl;
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = ctrl.alloc(4ull * kCtrlWords);

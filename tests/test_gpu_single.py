@@ -221,6 +221,21 @@ def test_shingle_prepass_orderings(prepass, window):
     check_sources(gr, g, inputs.sources(gr, seed=23, k=6))
 
 
+@pytest.mark.parametrize("case,max_grid,update", [("grid", 32, "eager"), ("grid", 64, "adaptive"),
+                                                   ("rmat", 8, "lazy"), ("rmat", 1, "auto")])
+def test_capped_grid(case, max_grid, update):
+    """A single-source launch capped to a few workgroups (cheaper grid barriers on
+    high-diameter graphs) gives the same levels."""
+    if case == "grid":
+        gr = inputs.grid_workload(200, 0.9, seed=31, permute_seed=32)
+        g = blest.Graph(gr, reorder="bandwidth", update=update, max_grid=max_grid)
+    else:
+        gr = inputs.rmat_workload(13, 16, seed=33, permute_seed=34)
+        g = blest.Graph(gr, reorder="compression", update=update, max_grid=max_grid)
+    assert g.stats()["grid"] == max_grid
+    check_sources(gr, g, inputs.sources(gr, seed=35, k=4))
+
+
 def _csr_arcs(gr, offset):
     rows = np.repeat(np.arange(gr.n, dtype=np.int64), np.diff(gr.row_ptr.astype(np.int64)))
     return rows + offset, gr.col.astype(np.int64) + offset
