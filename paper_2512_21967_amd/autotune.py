@@ -164,7 +164,8 @@ WORKLOADS = {
     "rmat22": dict(cands=candidates((8,), (1, 2, 4), (1, 2), ("lazy", "adaptive"), (0, 4096, 131072)),
                    k=1, nsrc=16),
     "grid4096": dict(cands=candidates((8,), (1, 2), (1, 2), ("eager",), (0,)), k=1, nsrc=4, max_grids=(0, 64, 32)),
-    "rmat16": dict(cands=candidates((8, 16), (1, 2, 4), (1, 2), UPDATES, (0, 256)), k=1, nsrc=16),
+    "rmat16": dict(cands=candidates((8, 16), (1, 2, 4), (1, 2), UPDATES, (0, 256)), k=1, nsrc=16,
+                   max_grids=(0, 128, 64)),
     "rmat20x64": dict(cands=candidates((8, 16, 32), (1, 2, 4), (2,), ("lazy",), (0,)), k=64, nsrc=64),
 }
 
