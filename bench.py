@@ -173,7 +173,8 @@ def single_workload(name):
     if name == "rmat22":
         gr = inputs.rmat_workload(22, 16, seed=1, permute_seed=2)
         return gr, dict(reorder="compression"), inputs.sources(gr, seed=3, k=64), \
-            "R-MAT scale 22 ef 16 (0.57,0.19,0.19,0.05), symmetrised, labels permuted, Algorithm 1 ordering (w=65536), 64 sources"
+            "R-MAT scale 22 ef 16 (0.57,0.19,0.19,0.05), symmetrised, labels permuted, shingle pre-pass and " \
+            "Algorithm 1 ordering, 64 sources"
     if name == "rmat16":
         gr = inputs.rmat_workload(16, 16, seed=1)
         return gr, dict(reorder="none"), inputs.sources(gr, seed=3, k=64), \
@@ -274,7 +275,7 @@ def run_single(args):
     config = {"workload": desc, "n": gr.n, "arcs": int(gr.nnz), "sources": len(sources), "update": st["update_used"],
               "sigma": st["sigma"], "tau": st["tau"], "ranges": st["nranges"], "grid": st["grid"],
               "block": st["block"], "compression": round(st["compression"], 4), "num_vss": st["num_vss"],
-              "prepass": "shingle" if st["prepass_used"] else None, "window": opts.get("window"),
+              "prepass": "shingle" if st["prepass_used"] else None, "window": st["window_used"] or None,
               "ms_per_bfs_mean": round(float(ms.mean()), 4), "ms_per_bfs_median": round(float(np.median(ms)), 4),
               "model_bytes_per_bfs": int(mb.mean()), "model_bytes_from": "oracle levels" if checked else "gpu levels",
               "eager_max": st["eager_max"] if st["update_used"] == "adaptive" else None, "group": opts.get("group", 2),

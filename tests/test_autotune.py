@@ -49,11 +49,24 @@ def test_store_and_lookup_round_trip(tmp_path):
     assert set(autotune.load(p)) == {"skewed-s11-k1", "mesh-s12-k1"}
 
 
+def test_grid_cap_is_stored_only_when_set(tmp_path):
+    p = os.path.join(tmp_path, "tuned.json")
+    gr = inputs.grid(64, 64, 0.9, seed=1)
+    capped = autotune.Trial(8, 1, 1, "eager", 3.0, 0, 64)
+    full = autotune.Trial(8, 1, 1, "eager", 4.0)
+    assert capped.options()["max_grid"] == 64 and "max_grid" not in full.options()
+    autotune.save(autotune.graph_key(gr), capped, [full, capped], "unit", path=p)
+    _, opts = autotune.lookup(gr, path=p)
+    assert opts["max_grid"] == 64
+    assert [c.get("max_grid", 0) for c in autotune.load(p)[autotune.graph_key(gr)]["candidates"]] == [64, 0]
+
+
 def test_committed_choices_are_valid_options():
     for key, rec in autotune.load().items():
         o = rec["options"]
         assert o["sigma"] in (8, 16, 32) and o["slots"] in (1, 2, 4, 8) and o["group"] in (1, 2, 4)
         assert o["update"] in ("eager", "lazy", "adaptive") and o["eager_max"] >= 0
+        assert o.get("max_grid", 0) >= 0
         assert rec["candidates"][0]["ms"] == rec["ms"]
 
 
