@@ -39,9 +39,6 @@ namespace {
 constexpr uint64_t kDenseFrac = 1;  // dense Stage 2 only when the queue holds every VSS
 constexpr uint32_t kStage2Rounds = 4;  // words per thread and pass of Stage 2
 
-__device__ __forceinline__ uint32_t sys_load(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
 // A poll of a host-written word: a relaxed system-scope load reads memory without
 // the cache invalidation an acquire at system scope costs; the control step issues
 // one acquire fence only when a poll shows new tickets.
