@@ -161,8 +161,8 @@ def autotune(csr, sources, *, k=1, cands=None, repeats=3, reorder="auto", window
 # candidate sets of the benchmark workloads (sigma = 8 is the paper's width; the
 # orderings take seconds per build at these sizes, so the layouts are few)
 WORKLOADS = {
-    "rmat22": dict(cands=candidates((8,), (1, 2, 4), (1, 2), ("lazy", "adaptive"), (0, 4096, 131072)),
-                   k=1, nsrc=16),
+    "rmat22": dict(cands=candidates((8,), (2, 4), (1, 2), ("lazy", "adaptive"), (0, 4096)),
+                   k=1, nsrc=16, max_grids=(0, 192, 128)),
     "grid4096": dict(cands=candidates((8,), (1, 2), (1, 2), ("eager",), (0,)), k=1, nsrc=4, max_grids=(0, 64, 32)),
     "rmat16": dict(cands=candidates((8, 16), (1, 2, 4), (1, 2), UPDATES, (0, 256)), k=1, nsrc=16,
                    max_grids=(0, 128, 64)),
