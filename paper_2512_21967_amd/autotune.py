@@ -163,6 +163,9 @@ def autotune(csr, sources, *, k=1, cands=None, repeats=3, reorder="auto", window
 WORKLOADS = {
     "rmat22": dict(cands=candidates((8,), (2, 4), (1, 2), ("lazy", "adaptive"), (0, 4096)),
                    k=1, nsrc=16, max_grids=(0, 192, 128)),
+    # wider slices for the same class: half the slice sets, 2-byte masks (unpacked)
+    "rmat22-wide": dict(cands=candidates((16, 32), (2, 4), (1,), ("lazy", "adaptive"), (0, 4096)),
+                        k=1, nsrc=16),
     "grid4096": dict(cands=candidates((8,), (1, 2), (1, 2), ("eager",), (0,)), k=1, nsrc=4, max_grids=(0, 64, 32)),
     "rmat16": dict(cands=candidates((8, 16), (1, 2, 4), (1, 2), UPDATES, (0, 256)), k=1, nsrc=16,
                    max_grids=(0, 128, 64)),
@@ -179,7 +182,7 @@ def main():
     ap.add_argument("--out", default=TUNED_PATH, help="store to update (default: the package's tuned.json)")
     args = ap.parse_args()
     w = WORKLOADS[args.workload]
-    if args.workload == "rmat22":
+    if args.workload in ("rmat22", "rmat22-wide"):
         gr, reorder = inputs.rmat_workload(22, 16, seed=1, permute_seed=2), "compression"
         src = inputs.sources(gr, seed=3, k=64)[:w["nsrc"]]
     elif args.workload == "grid4096":
