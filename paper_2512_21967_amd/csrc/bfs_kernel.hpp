@@ -746,11 +746,15 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
   grid_barrier(ctrl);
 
   bool prev_eager = false, prev2_eager = false;  // modes of levels l - 1 and l - 2 (adaptive)
+  // The queue lengths of this level and of the one before, carried from the check
+  // that ends each level (a fresh load would cost another round trip per level;
+  // the slots do not change in between).  The initial queue is q0n long; the
+  // queue before it is empty.
+  uint32_t len = q0n, prev_len = 0;
   for (int32_t level = 1; level <= (int32_t)p.n + 1; ++level) {
     if (MODE == kLazy) {
       const uint2* qc = reinterpret_cast<const uint2*>(p.queue) + ((level - 1) & 1) * p.qcap;
       uint2* qn = reinterpret_cast<uint2*>(p.queue) + (level & 1) * p.qcap;
-      const uint32_t len = ld_relaxed(qlen + ((level - 1) % 3) * kLine);
       uint32_t* qnext_len = qlen + (level % 3) * kLine;
       if (tid == 0) __hip_atomic_store(qlen + ((level + 1) % 3) * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (LDSVIS)
@@ -760,13 +764,14 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
       grid_barrier(ctrl);
       stage2_lazy<SIG>(p, qn, qnext_len, level);
       grid_barrier(ctrl);
-      if (ld_relaxed(qnext_len) == 0) break;
+      prev_len = len;
+      len = ld_relaxed(qnext_len);
+      if (len == 0) break;
     } else if (MODE == kEager) {
       const uint32_t* qc = p.queue + ((level - 1) % 3) * p.qcap;
       uint32_t* qn = p.queue + (level % 3) * p.qcap;
       const uint32_t* qold = p.queue + ((level + 1) % 3) * p.qcap;  // queue of level - 2
-      const uint32_t len = ld_relaxed(qlen + ((level - 1) % 4) * kLine);
-      const uint32_t old_len = ld_relaxed(qlen + ((level + 2) % 4) * kLine);
+      const uint32_t old_len = prev_len;
       uint32_t* qnext_len = qlen + (level % 4) * kLine;
       if (tid == 0) __hip_atomic_store(qlen + ((level + 1) % 4) * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const uint32_t* fc = p.front + ((level - 1) % 3) * p.n_words;
@@ -775,20 +780,20 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
       clear_chunks<SIG>(p, fold, qold, old_len);
       stage1_eager<MT, SLOTS, G>(p, qc, len, fc, fn, qn, qnext_len, level);
       grid_barrier(ctrl);
-      if (ld_relaxed(qnext_len) == 0) break;
+      prev_len = len;
+      len = ld_relaxed(qnext_len);
+      if (len == 0) break;
     } else {
       uint2* q2 = reinterpret_cast<uint2*>(p.queue);
       const uint2* qc = q2 + ((level - 1) % 3) * p.qcap;
       uint2* qn = q2 + (level % 3) * p.qcap;
-      const uint32_t len = ld_relaxed(qlen + ((level - 1) % 4) * kLine);
       uint32_t* qnext_len = qlen + (level % 4) * kLine;
       if (tid == 0) __hip_atomic_store(qlen + ((level + 1) % 4) * kLine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const uint32_t* fc = prev_eager ? p.front + ((level - 1) % 3) * p.n_words : nullptr;
       if (prev2_eager) {
         // the claims of level - 2 (sets of the queue it pushed) leave their bitmap
         const uint2* qold = q2 + ((level + 1) % 3) * p.qcap;
-        clear_chunks<SIG>(p, p.front + ((level + 1) % 3) * p.n_words, qold,
-                          ld_relaxed(qlen + ((level + 2) % 4) * kLine));
+        clear_chunks<SIG>(p, p.front + ((level + 1) % 3) * p.n_words, qold, prev_len);
       }
       const bool eager = len < p.eager_max;
       if (eager) {
@@ -803,7 +808,9 @@ __global__ __launch_bounds__(1024) void bfs_persistent(BfsParams p) {
         stage2_lazy<SIG>(p, qn, qnext_len, level);
         grid_barrier(ctrl);
       }
-      if (ld_relaxed(qnext_len) == 0) break;
+      prev_len = len;
+      len = ld_relaxed(qnext_len);
+      if (len == 0) break;
       prev2_eager = prev_eager;
       prev_eager = eager;
     }
