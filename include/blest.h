@@ -7,9 +7,9 @@
  *     the transposed graph (Section 2).
  *   - Slices, slice sets and virtual slice sets (Sections 2 and 2.1); column-major
  *     placement of a VSS's row-sorted slices (Section 2.1.2).
- *   - Compression-oriented reordering (Algorithm 1, JaccardWithWindows) for
- *     social-like graphs and bandwidth-reducing reordering (RCM) otherwise
- *     (Sections 2.2 and 2.2.1).
+ *   - Compression-oriented reordering (Algorithm 1, JaccardWithWindows, after a
+ *     locality pre-pass where the paper runs Gorder) for social-like graphs and
+ *     bandwidth-reducing reordering (RCM) otherwise (Sections 2.2 and 2.2.1).
  *   - The eager kernel (Algorithm 2) and the lazy vertex-update kernel
  *     (Algorithm 3, Section 3.2), all levels fused into one persistent launch
  *     (Section 3.3).
